@@ -1,0 +1,39 @@
+"""FP64 CPU oracle for data-parallel brick volume rendering and sort-last compositing.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or link
+this package: only the test suite, the smoke check and the benchmark's CPU
+baseline leg use it.  It shares no code with the GPU path (no kernels, headers,
+tables or helpers); the two meet only through the seeded inputs of ``synth``.
+
+What it computes, and where the paper fixes it:
+
+* Sort-last compositing of one RGBA-z fragment per pixel per rank, sorted by
+  depth and merged front to back (paper section 2.1, Data Parallel Rendering;
+  section 5.1.1, Compositing: every fragment carries RGBA *and* depth, so no
+  fixed compositing order is needed).  ``composite.py``.
+* The per-rank local render that produces those fragments.  The paper leaves it
+  to "any device that computes colour and depth" (section 5.1.2, Rendering), so
+  its definition here is a reading: fixed-step emission-absorption quadrature on
+  an eye-anchored sample lattice, trilinear sampling with clamp-to-edge at the
+  global domain, a 1D RGBA transfer function, per-brick ray/box clipping,
+  early ray termination and depth = brick entry distance.  ``render.py``.
+* Macrocell value ranges and transfer-function majorants used by empty-space
+  skipping (decided in FP32, the kernel's precision).  ``macrocell.py``.
+* Gradients of an L2 image loss with respect to the density grid and the
+  transfer-function table.  ``grad.py``.
+* An independent loop-based brute-force renderer for tiny inputs.  ``brute.py``.
+
+Pins (tests marked ``not gpu``): closed-form transmittance of a constant volume,
+O(dt^2) convergence to the analytic integral of an affine field, brute force on
+tiny grids, the split invariant (one brick == k bricks with ghosts, composited),
+composite closed forms and permutation invariance, numpy min/max for macrocell
+ranges, finite differences and torch.autograd (FP64) for gradients.
+"""
+
+from .render import (  # noqa: F401
+    RenderParams, camera_basis, camera_rays, clip_box, trilinear, tf_lookup,
+    march_rays, render_brick, render_image,
+)
+from .composite import composite  # noqa: F401
+from .macrocell import macrocell_ranges, majorants, macrocell_grid  # noqa: F401
+from .grad import loss_and_grad, forward_image  # noqa: F401
