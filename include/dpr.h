@@ -1,0 +1,241 @@
+/*
+ * dpr.h -- C ABI of the MI355X-native data-parallel volume renderer and
+ * sort-last compositor.
+ *
+ * The calls follow the data-parallel rendering paradigm of "Standardized
+ * Data-Parallel Rendering Using ANARI" (arXiv 2407.00179):
+ *   - world content (bricks) is local to a rank and added piece by piece
+ *     (section 3.1.2, Locally Defined Objects);
+ *   - camera and renderer parameters are global and identical for every brick
+ *     (section 3.1.1, Globally Consistent Objects);
+ *   - rendering a frame is the one collective step: every local piece is
+ *     rendered to an RGBA-z fragment per pixel and the fragments are composited
+ *     in per-pixel depth order (section 3.2, Collaborative Operations;
+ *     section 5.1.1, Compositing);
+ *   - the finished frame is mapped where the caller asks for it
+ *     (section 3.1.3, Locally Mapped Frame Buffers);
+ *   - the partition is described by the application through per-piece bounds
+ *     (section 8.2, Scene/Data Partitioning).
+ * On one GPU each brick stands for one rank's share.  The local render itself
+ * (emission-absorption ray marching) is not specified by the paper; its exact
+ * definition is given with dpr_render_partial below.
+ *
+ * Conventions
+ *   - Every call returns dpr_status; out-parameters are written only on
+ *     success.  No C++ exception crosses the ABI.  dpr_last_error() returns a
+ *     thread-local message for the last failing call on this thread.
+ *   - Volumes are scalar grids of global dims (nx, ny, nz), x fastest.  Voxel
+ *     (i,j,k) is the centre of cell [i,i+1)x[j,j+1)x[k,k+1); with
+ *     h = 1/max(nx,ny,nz) the world box is [0,nx h]x[0,ny h]x[0,nz h].
+ *   - A frame of W x H pixels is float RGBA premultiplied colour (16 B per
+ *     pixel, row-major, row 0 at the top) plus float depth (4 B per pixel).
+ *     An empty pixel is (0,0,0,0) at depth +inf.
+ *   - Render and composite calls enqueue work on the device's HIP stream and
+ *     return; HIP errors of that work surface as DPR_ERR_DEVICE at the next
+ *     synchronising call (dpr_device_sync, dpr_frame_map, dpr_frame_read), the
+ *     way an asynchronous render is followed by a map.
+ *   - A device handle and the objects made from it are not thread-safe; the
+ *     caller serialises calls on one device.
+ */
+#ifndef DPR_H
+#define DPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DPR_OK = 0,
+  DPR_ERR_INVALID_ARGUMENT = -1,
+  DPR_ERR_INVALID_STATE = -2,
+  DPR_ERR_OUT_OF_MEMORY = -3,
+  DPR_ERR_DEVICE = -4,
+  DPR_ERR_UNSUPPORTED = -5
+} dpr_status;
+
+typedef enum { DPR_F32 = 0, DPR_F16 = 1 } dpr_dtype;
+
+/* render-parameter and call flags */
+#define DPR_FLAG_NO_SKIP 0x1u    /* disable macrocell empty-space skipping          */
+#define DPR_FLAG_PLAIN 0x2u      /* batch: one plain launch per (camera, brick)      */
+#define DPR_FLAG_NO_GRAPH 0x4u   /* batch: enqueue directly, no HIP graph replay     */
+
+typedef struct dpr_device_t* dpr_device; /* one GPU + one HIP stream              */
+typedef struct dpr_world_t* dpr_world;   /* this rank's bricks + TF + camera      */
+typedef struct dpr_frame_t* dpr_frame;   /* W x H RGBA + depth (+ sample counts)  */
+
+/* Pinhole camera: rays through pixel centres, vertical field of view fovy_deg.
+ * f = normalize(center - eye), r = normalize(f x up), u = r x f,
+ * d = normalize(f + x r + y u) with x = (2(px+.5)/W - 1) tan(fovy/2) W/H and
+ * y = (1 - 2(py+.5)/H) tan(fovy/2).                                            */
+typedef struct {
+  double eye[3], center[3], up[3];
+  double fovy_deg;
+  int32_t width, height;
+} dpr_camera;
+
+/* step_voxels: lattice step dt = step_voxels * h, in (0, 1].
+ * ert_threshold: stop a ray once 1 - T >= threshold; >= 1 disables.
+ * macrocell_cells: macrocell edge in cells (power of two in [2, 64]).
+ * flags: DPR_FLAG_NO_SKIP.                                                      */
+typedef struct {
+  float step_voxels;
+  float ert_threshold;
+  int32_t macrocell_cells;
+  uint32_t flags;
+} dpr_render_params;
+
+const char* dpr_last_error(void);
+const char* dpr_version(void);
+
+/* ---------------------------------------------------------------- device */
+/* Bind GPU `hip_device` and the HIP stream `hip_stream` (NULL: the null stream).
+ * Fails with DPR_ERR_DEVICE when no such GPU is visible.                        */
+dpr_status dpr_device_create(int hip_device, void* hip_stream, dpr_device* out);
+dpr_status dpr_device_set_stream(dpr_device, void* hip_stream);
+dpr_status dpr_device_sync(dpr_device);
+void dpr_device_release(dpr_device);
+/* number of compute units and the wavefront size of the bound GPU */
+dpr_status dpr_device_info(dpr_device, int32_t* cu_count, int32_t* wave_size);
+
+/* ---------------------------------------------------------------- world */
+dpr_status dpr_world_create(dpr_device, const int64_t global_dims[3], dpr_world* out);
+void dpr_world_release(dpr_world);
+
+/* Add one locally owned brick (section 3.1.2): global cells [owned_lo, owned_hi)
+ * per axis plus ghost_lo/ghost_hi stored voxel layers outside them.  `voxels`
+ * holds the stored region, dims = owned_hi - owned_lo + ghost_lo + ghost_hi,
+ * x fastest, in host memory (voxels_on_device = 0) or device memory (1).  The
+ * data are copied; the caller may free its buffer on return.  Every global dim
+ * must be >= 2.  Ghost layers may not reach outside the global domain.
+ * brick_id receives the brick's index (0, 1, ...), which is also its intrinsic
+ * fragment id for compositing.  Adding a brick un-commits the world.            */
+dpr_status dpr_world_add_brick(dpr_world, const void* voxels, dpr_dtype dtype, int voxels_on_device,
+                               const int64_t owned_lo[3], const int64_t owned_hi[3],
+                               const int32_t ghost_lo[3], const int32_t ghost_hi[3], int32_t* brick_id);
+
+/* Validate the partition and build device data.  Owned boxes must be pairwise
+ * disjoint axis-aligned boxes (each rank's data convex: the condition under
+ * which one fragment per pixel composites correctly, section 2.1), and every
+ * owned face interior to the global domain must carry >= 1 ghost layer
+ * (samples fall up to half a step, at most half a voxel, outside the owned
+ * box, and trilinear reads one voxel beyond that).  Then
+ * each brick is re-tiled into 8^3-voxel blocks and its macrocell min/max
+ * ranges are built (window [mc*m - 1, mc*m + mc] of owned-relative voxels).
+ * Gaps between bricks are allowed and render empty.                             */
+dpr_status dpr_world_commit(dpr_world);
+
+/* Transfer function: n_entries RGBA floats (host), entry i at value
+ * value_lo + i (value_hi - value_lo)/(n_entries - 1); RGB is emitted colour,
+ * A is normalised extinction; extinction per world unit = density_scale * A.
+ * 2 <= n_entries <= 1024, value_hi > value_lo, density_scale >= 0.              */
+dpr_status dpr_set_transfer_function(dpr_world, const float* rgba, int32_t n_entries, float value_lo,
+                                     float value_hi, float density_scale);
+/* Global camera (section 3.1.1: identical for every brick).                     */
+dpr_status dpr_set_camera(dpr_world, const dpr_camera*);
+dpr_status dpr_set_render_params(dpr_world, const dpr_render_params*);
+
+/* Host-only validators (no GPU needed): the partition rules dpr_world_commit
+ * applies (n bricks; lo/hi/ghost arrays hold 3 values per brick, x y z), and the
+ * camera rules dpr_set_camera applies.                                          */
+dpr_status dpr_check_partition(const int64_t global_dims[3], int32_t n, const int64_t* owned_lo,
+                               const int64_t* owned_hi, const int32_t* ghost_lo, const int32_t* ghost_hi);
+dpr_status dpr_check_camera(const dpr_camera*);
+
+/* Read back brick info and macrocell data (host copies; synchronises).
+ * ranges: float2 (min, max) per macrocell, majorant: float per macrocell, both
+ * x-fastest over the brick's macrocell grid mc_dims; either pointer may be NULL.
+ * The majorant reflects the current transfer function.                         */
+dpr_status dpr_world_brick_macrocells(dpr_world, int32_t brick_id, int32_t mc_dims[3], float* ranges,
+                                      float* majorant, size_t capacity);
+dpr_status dpr_world_brick_count(dpr_world, int32_t* n);
+
+/* ---------------------------------------------------------------- frames */
+dpr_status dpr_frame_create(dpr_device, int32_t width, int32_t height, dpr_frame* out);
+/* Borrow caller buffers (device memory, 16 B and 4 B per pixel); they must
+ * outlive the frame.                                                            */
+dpr_status dpr_frame_wrap(dpr_device, int32_t width, int32_t height, float* rgba_dev, float* depth_dev,
+                          dpr_frame* out);
+/* Optional per-pixel logical-sample counts (int32, device memory, borrowed):
+ * renders into this frame also store, per pixel, the number of lattice
+ * segments of positive length processed before termination.  NULL detaches.   */
+dpr_status dpr_frame_attach_counts(dpr_frame, int32_t* counts_dev);
+/* Synchronise and return the frame's DEVICE pointers.                           */
+dpr_status dpr_frame_map(dpr_frame, const float** rgba_dev, const float** depth_dev);
+dpr_status dpr_frame_unmap(dpr_frame);
+/* Synchronise and copy the frame to host buffers (either may be NULL).          */
+dpr_status dpr_frame_read(dpr_frame, float* rgba_host, float* depth_host);
+void dpr_frame_release(dpr_frame);
+
+/* ---------------------------------------------------------------- rendering */
+/* Render brick `brick_id` into `out` (one RGBA-z fragment per pixel; the
+ * "local rendering" of section 5.1.2).  Definition (FP32 arithmetic, FP64 ray
+ * geometry):
+ *   ray/box clip against the owned box [lo h, hi h] -> [t_in, t_out], hit iff
+ *   t_out > t_in; lattice segments s in [floor(t_in/dt), ceil(t_out/dt) - 1]
+ *   anchored at the eye, clipped to length l_s; the field is sampled once per
+ *   segment at t = (s + 1/2) dt by trilinear interpolation in global voxel-centre
+ *   coordinates clamped to [0, n-1]; the TF is interpolated linearly;
+ *   tau = D A l_s; C += T (1 - e^-tau) rgb; T *= e^-tau; stop once 1 - T >= ert.
+ *   Output (C, 1 - T) at depth t_in; a miss writes (0,0,0,0) at +inf.
+ * Segments whose sample point lies in a macrocell of majorant 0 are skipped;
+ * they contribute exactly nothing, so skipping never changes a result.
+ * The frame must match the camera's size.                                       */
+dpr_status dpr_render_partial(dpr_world, int32_t brick_id, dpr_frame out);
+
+/* Sort-last composite (section 2.1; section 5.1.1): for each pixel, the k
+ * fragments with finite depth are sorted by (depth, frag_id) and composited
+ * front to back, C += T rgb_i, T *= (1 - alpha_i); output (C, 1 - T) at the
+ * minimum depth.  frag_ids are intrinsic ids (e.g. brick or rank), so the
+ * result does not depend on the order of `parts`; they must be distinct.
+ * 1 <= k <= 256; all frames and `out` have the same size; `out` may not alias
+ * a part.  frag_ids may be NULL (ids 0..k-1).                                   */
+dpr_status dpr_composite(dpr_device, const dpr_frame* parts, const int32_t* frag_ids, int32_t k,
+                         dpr_frame out);
+
+/* The collective render of section 3.2 on one GPU: render every brick of the
+ * world into its own partial frame, then composite them into `out`.           */
+dpr_status dpr_render_frame(dpr_world, dpr_frame out);
+
+/* Batched render of n cameras: one persistent launch walks a queue of
+ * (camera, brick, screen tile) items, then a tile compositor merges each
+ * camera's fragments into outs[c]; replayed from a HIP graph captured on the
+ * first call for these frames (flags: DPR_FLAG_PLAIN, DPR_FLAG_NO_GRAPH).
+ * The results equal dpr_render_frame per camera bit for bit.                   */
+dpr_status dpr_render_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_frame* outs, uint32_t flags);
+/* Time the candidate tile shapes for this world and camera batch on the GPU and
+ * keep the fastest for later dpr_render_batch calls; writes the chosen shape.  */
+dpr_status dpr_autotune_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_frame* outs,
+                              int32_t* tile_w, int32_t* tile_h);
+/* Force a tile shape (tile_w * tile_h must be 64, a multiple of 64, <= 1024).  */
+dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
+
+/* ---------------------------------------------------------------- training */
+/* Differentiable render of one whole volume (no bricks, ERT off) for n cameras.
+ * volume: FP32 device grid of dims (x fastest); tf: n_tf RGBA FP32 (device).
+ * out_rgba (n*H*W*4) / out_depth (n*H*W) are device buffers; `workspace`
+ * (device, ws_bytes >= dpr_train_workspace_size) receives, per ray, the total
+ * optical depth and a checkpoint every 64 segments, read by the backward pass.  */
+dpr_status dpr_train_workspace_size(const int64_t dims[3], const dpr_camera* cams, int32_t n, float step_voxels,
+                                    size_t* bytes);
+dpr_status dpr_render_train_forward(dpr_device, const float* volume, const int64_t dims[3], const float* tf,
+                                    int32_t n_tf, float value_lo, float value_hi, float density,
+                                    const dpr_render_params*, const dpr_camera* cams, int32_t n,
+                                    float* out_rgba, float* out_depth, void* workspace, size_t ws_bytes);
+/* Adjoint: given dL/d(out_rgba) (device, n*H*W*4), ACCUMULATE (+=) dL/dvolume
+ * and dL/dtf into the device buffers grad_volume / grad_tf.  Reverse traversal
+ * per ray: transmittance is recomputed from the stored total optical depth by
+ * subtracting segment depths, restored exactly at every checkpoint.            */
+dpr_status dpr_render_backward(dpr_device, const float* volume, const int64_t dims[3], const float* tf,
+                               int32_t n_tf, float value_lo, float value_hi, float density,
+                               const dpr_render_params*, const dpr_camera* cams, int32_t n,
+                               const float* grad_rgba, const void* workspace, size_t ws_bytes,
+                               float* grad_volume, float* grad_tf);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPR_H */

@@ -170,9 +170,11 @@ def march_rays(data, stored_lo, dims, owned_lo, owned_hi, tf, params: RenderPara
         ell = seg_hi - seg_lo
         valid = ell > 0.0
         tm = (s + 0.5) * dt
-        p = o[act] + tm[:, None] * d[act]
-        v = trilinear(data, stored_lo, dims, p / h - 0.5)
-        rgba = tf_lookup(tf, v, params.tf_lo, params.tf_hi)
+        rgba = np.zeros((act.size, 4))
+        if valid.any():
+            p = o[act[valid]] + tm[valid, None] * d[act[valid]]
+            v = trilinear(data, stored_lo, dims, p / h - 0.5)
+            rgba[valid] = tf_lookup(tf, v, params.tf_lo, params.tf_hi)
         tau = np.where(valid, D * rgba[:, 3] * ell, 0.0)
         e = np.exp(-tau)
         a = -np.expm1(-tau)

@@ -1,0 +1,220 @@
+"""MI355X-native data-parallel volume rendering and sort-last compositing.
+
+Python face of the C ABI in ``include/dpr.h``.  Every step of rendering and
+compositing runs in the HIP kernels of ``libdpr.so``; this module only passes
+pointers, sizes and the current torch stream.  torch supplies device memory and
+streams, nothing else.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _native as N
+from ._native import DprError, F16, F32, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, check, lib  # noqa: F401
+
+__all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_camera"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class Params:
+    step_voxels: float = 0.5
+    ert_threshold: float = 0.99
+    macrocell_cells: int = 16
+    flags: int = 0
+
+    def c(self):
+        return N.RenderParams(self.step_voxels, self.ert_threshold, self.macrocell_cells, self.flags)
+
+
+def to_c_camera(cam):
+    """Any object with eye, center, up, fovy_deg, width, height -> dpr_camera."""
+    return N.Camera((C.c_double * 3)(*cam.eye), (C.c_double * 3)(*cam.center), (C.c_double * 3)(*cam.up),
+                    float(cam.fovy_deg), int(cam.width), int(cam.height))
+
+
+class Device:
+    """One GPU plus the HIP stream the library enqueues on (torch's current stream by default)."""
+
+    def __init__(self, index=0, stream=None):
+        torch = _torch()
+        self.index = index
+        self.torch_device = torch.device("cuda", index)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        check(lib.dpr_device_create(index, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        check(lib.dpr_device_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def sync(self):
+        check(lib.dpr_device_sync(self.h))
+
+    def info(self):
+        cu, ws = C.c_int32(), C.c_int32()
+        check(lib.dpr_device_info(self.h, C.byref(cu), C.byref(ws)))
+        return cu.value, ws.value
+
+    def release(self):
+        if self.h:
+            lib.dpr_device_release(self.h)
+            self.h = None
+
+
+class Frame:
+    """W x H premultiplied RGBA + depth held in torch tensors (borrowed by the library)."""
+
+    def __init__(self, dev: Device, width, height, rgba=None, depth=None, counts=False):
+        torch = _torch()
+        self.dev = dev
+        self.width, self.height = int(width), int(height)
+        if rgba is None:
+            rgba = torch.empty((self.height, self.width, 4), dtype=torch.float32, device=dev.torch_device)
+        if depth is None:
+            depth = torch.empty((self.height, self.width), dtype=torch.float32, device=dev.torch_device)
+        assert rgba.is_contiguous() and depth.is_contiguous()
+        assert rgba.dtype == torch.float32 and depth.dtype == torch.float32
+        assert rgba.numel() == 4 * self.width * self.height and depth.numel() == self.width * self.height
+        self.rgba, self.depth = rgba, depth
+        h = C.c_void_p()
+        check(lib.dpr_frame_wrap(dev.h, self.width, self.height, C.c_void_p(rgba.data_ptr()),
+                                 C.c_void_p(depth.data_ptr()), C.byref(h)))
+        self.h = h
+        self.counts = None
+        if counts:
+            self.attach_counts()
+
+    def attach_counts(self, counts=None):
+        torch = _torch()
+        if counts is None:
+            counts = torch.zeros((self.height, self.width), dtype=torch.int32, device=self.dev.torch_device)
+        self.counts = counts
+        check(lib.dpr_frame_attach_counts(self.h, C.c_void_p(counts.data_ptr())))
+        return counts
+
+    def release(self):
+        if self.h:
+            lib.dpr_frame_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def _as_bytes_ptr(arr, dev):
+    """Host numpy array or device torch tensor -> (pointer, on_device, dtype code, keepalive)."""
+    torch = _torch()
+    if isinstance(arr, torch.Tensor):
+        assert arr.is_contiguous()
+        code = {torch.float32: F32, torch.float16: F16}[arr.dtype]
+        on_dev = arr.is_cuda
+        return C.c_void_p(arr.data_ptr()), int(on_dev), code, arr
+    a = np.ascontiguousarray(arr)
+    code = {np.dtype(np.float32): F32, np.dtype(np.float16): F16}[a.dtype]
+    return C.c_void_p(a.ctypes.data), 0, code, a
+
+
+class World:
+    """This rank's bricks, transfer function and camera (section 3.1 of the paper)."""
+
+    def __init__(self, dev: Device, dims):
+        self.dev = dev
+        self.dims = tuple(int(v) for v in dims)
+        h = C.c_void_p()
+        check(lib.dpr_world_create(dev.h, N.I64x3(*self.dims), C.byref(h)))
+        self.h = h
+        self.params = Params()
+
+    def add_brick(self, voxels, lo, hi, ghost_lo=(0, 0, 0), ghost_hi=(0, 0, 0)):
+        ptr, on_dev, code, keep = _as_bytes_ptr(voxels, self.dev)
+        bid = C.c_int32()
+        check(lib.dpr_world_add_brick(self.h, ptr, code, on_dev, N.I64x3(*lo), N.I64x3(*hi), N.I32x3(*ghost_lo),
+                                      N.I32x3(*ghost_hi), C.byref(bid)))
+        del keep
+        return bid.value
+
+    def commit(self):
+        check(lib.dpr_world_commit(self.h))
+
+    def set_transfer_function(self, tf, lo=0.0, hi=1.0, density=20.0):
+        t = np.ascontiguousarray(tf, dtype=np.float32)
+        check(lib.dpr_set_transfer_function(self.h, C.c_void_p(t.ctypes.data), t.shape[0], lo, hi, density))
+
+    def set_camera(self, cam):
+        c = to_c_camera(cam)
+        check(lib.dpr_set_camera(self.h, C.byref(c)))
+
+    def set_params(self, params: Params):
+        self.params = params
+        c = params.c()
+        check(lib.dpr_set_render_params(self.h, C.byref(c)))
+
+    def brick_count(self):
+        n = C.c_int32()
+        check(lib.dpr_world_brick_count(self.h, C.byref(n)))
+        return n.value
+
+    def macrocells(self, brick_id):
+        md = N.I32x3()
+        check(lib.dpr_world_brick_macrocells(self.h, brick_id, md, None, None, 0))
+        cnt = md[0] * md[1] * md[2]
+        ranges = np.empty((md[2], md[1], md[0], 2), dtype=np.float32)
+        maj = np.empty((md[2], md[1], md[0]), dtype=np.float32)
+        check(lib.dpr_world_brick_macrocells(self.h, brick_id, md, C.c_void_p(ranges.ctypes.data),
+                                             C.c_void_p(maj.ctypes.data), cnt))
+        return ranges, maj
+
+    def render_partial(self, brick_id, frame: Frame):
+        check(lib.dpr_render_partial(self.h, brick_id, frame.h))
+
+    def render_frame(self, frame: Frame):
+        check(lib.dpr_render_frame(self.h, frame.h))
+
+    def render_batch(self, cams, frames, flags=0):
+        arr = (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])
+        fr = (C.c_void_p * len(frames))(*[f.h.value for f in frames])
+        check(lib.dpr_render_batch(self.h, arr, len(cams), fr, flags))
+
+    def autotune_batch(self, cams, frames):
+        arr = (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])
+        fr = (C.c_void_p * len(frames))(*[f.h.value for f in frames])
+        tw, th = C.c_int32(), C.c_int32()
+        check(lib.dpr_autotune_batch(self.h, arr, len(cams), fr, C.byref(tw), C.byref(th)))
+        return tw.value, th.value
+
+    def set_batch_tile(self, tw, th):
+        check(lib.dpr_set_batch_tile(self.h, tw, th))
+
+    def release(self):
+        if self.h:
+            lib.dpr_world_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def composite(dev: Device, parts, out: Frame, ids=None):
+    """Sort-last composite of ``parts`` (Frames) into ``out``; ids are intrinsic fragment ids."""
+    k = len(parts)
+    fr = (C.c_void_p * k)(*[f.h.value for f in parts])
+    idarr = None if ids is None else (C.c_int32 * k)(*[int(i) for i in ids])
+    check(lib.dpr_composite(dev.h, fr, idarr, k, out.h))

@@ -1,0 +1,86 @@
+// Device-side data structures and helpers shared by the HIP kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace dpr {
+
+constexpr int kBlockEdge = 8;         // bricks are stored as 8^3-voxel blocks
+constexpr int kBlockVoxels = 512;
+constexpr int kMaxTF = 1024;          // transfer-function entries held in LDS
+
+// Pinhole camera in FP64: ray d = normalize(f + x r + y u) with
+// x = (2(px+.5)/W - 1) sx and y = (1 - 2(py+.5)/H) sy.
+struct CamG {
+  double eye[3];
+  double f[3], r[3], u[3];
+  double sx, sy;
+  int W, H;
+};
+
+// One brick as the kernels see it.
+struct BrickG {
+  const void* data;       // 8^3-blocked voxels (x fastest inside a block, blocks x-fastest)
+  int slo[3];             // global voxel index of stored voxel (0,0,0)
+  int sdim[3];            // stored dims
+  uint32_t bsy, bsz;      // element stride of one block row in y / one block slab in z
+  int olo[3], ohi[3];     // owned global cells [olo, ohi)
+  const float* majorant;  // per macrocell, x fastest (may be null when skipping is off)
+  int mdim[3];            // macrocell grid
+  int mc_shift;           // log2(macrocell edge)
+};
+
+// Scene-wide render constants.
+struct SceneG {
+  int dims[3];            // global dims
+  double h, inv_h, dt;
+  float dt_f, density, ert, tf_lo, tf_scale;  // tf_scale = (N-1)/(hi-lo)
+  int ntf;
+};
+
+__device__ __forceinline__ uint32_t blk_x(int i) { return ((uint32_t)(i >> 3) << 9) + (uint32_t)(i & 7); }
+__device__ __forceinline__ uint32_t blk_y(int j, uint32_t bsy) { return (uint32_t)(j >> 3) * bsy + (uint32_t)((j & 7) << 3); }
+__device__ __forceinline__ uint32_t blk_z(int k, uint32_t bsz) { return (uint32_t)(k >> 3) * bsz + (uint32_t)((k & 7) << 6); }
+
+template <typename T> __device__ __forceinline__ float load_voxel(const T* p, uint32_t off);
+template <> __device__ __forceinline__ float load_voxel<float>(const float* p, uint32_t off) { return p[off]; }
+template <> __device__ __forceinline__ float load_voxel<__half>(const __half* p, uint32_t off) {
+  return __half2float(p[off]);
+}
+
+// Ray through pixel (px, py); returns the unit direction.
+__device__ __forceinline__ void camera_ray(const CamG& c, int px, int py, double d[3]) {
+  double x = (2.0 * (px + 0.5) / c.W - 1.0) * c.sx;
+  double y = (1.0 - 2.0 * (py + 0.5) / c.H) * c.sy;
+  double v0 = c.f[0] + x * c.r[0] + y * c.u[0];
+  double v1 = c.f[1] + x * c.r[1] + y * c.u[1];
+  double v2 = c.f[2] + x * c.r[2] + y * c.u[2];
+  double inv = 1.0 / sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+  d[0] = v0 * inv;
+  d[1] = v1 * inv;
+  d[2] = v2 * inv;
+}
+
+// Slab test against the box [lo, hi]; t_in = max(t_near, 0), hit iff t_out > t_in.
+__device__ __forceinline__ bool clip_box(const double o[3], const double d[3], const double lo[3],
+                                         const double hi[3], double& t_in, double& t_out) {
+  double tn = -INFINITY, tf = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) {
+      if (o[a] < lo[a] || o[a] > hi[a]) return false;
+      continue;
+    }
+    double t0 = (lo[a] - o[a]) / d[a];
+    double t1 = (hi[a] - o[a]) / d[a];
+    tn = fmax(tn, fmin(t0, t1));
+    tf = fmin(tf, fmax(t0, t1));
+  }
+  t_in = fmax(tn, 0.0);
+  t_out = tf;
+  return t_out > t_in;
+}
+
+}  // namespace dpr

@@ -1,0 +1,29 @@
+// Host-side launchers of the HIP kernels (all enqueue on the given stream).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace dpr {
+
+hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
+                           int bz, hipStream_t st);
+hipError_t launch_macrocells(const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st);
+hipError_t launch_majorants(const float2* ranges, int count, const float4* tf, int ntf, float lo, float hi,
+                            float* maj, hipStream_t st);
+hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, const float4* tf, bool f16, bool skip,
+                        float4* rgba, float* depth, int* count, hipStream_t st);
+
+// Composite table: per fragment list entry, the frame pointers and the rank of
+// its intrinsic id among the k ids (ties in depth are broken by that rank).
+constexpr int kMaxFrags = 256;
+struct CompTable {
+  const float4* rgba[kMaxFrags];
+  const float* depth[kMaxFrags];
+  int idrank[kMaxFrags];
+};
+hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
+                            hipStream_t st);
+
+}  // namespace dpr

@@ -1,0 +1,707 @@
+// C ABI implementation: devices, worlds, bricks, frames, validation and the
+// per-brick render / composite entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+#include "runtime.hpp"
+
+namespace dpr {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  if (log_enabled()) fprintf(stderr, "[dpr] %s\n", buf);
+}
+
+dpr_status fail(dpr_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  if (log_enabled()) fprintf(stderr, "[dpr] %s\n", buf);
+  return st;
+}
+
+dpr_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(DPR_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+  return fail(DPR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool log_enabled() {
+  static int on = -1;
+  if (on < 0) {
+    const char* s = getenv("DPR_LOG");
+    on = (s && s[0] == '1') ? 1 : 0;
+  }
+  return on == 1;
+}
+
+static long g_alloc_count = 0;
+
+dpr_status dev_alloc(void** p, size_t bytes, const char* what) {
+  ++g_alloc_count;
+  const char* fi = getenv("DPR_FAULT_INJECT");
+  if (fi && strncmp(fi, "alloc:", 6) == 0 && atol(fi + 6) == g_alloc_count)
+    return fail(DPR_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (allocation %ld)", what, g_alloc_count);
+  hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(DPR_ERR_OUT_OF_MEMORY, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  return DPR_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------- geometry helpers
+CamG make_cam(const dpr_camera& c) {
+  CamG g{};
+  double f[3] = {c.center[0] - c.eye[0], c.center[1] - c.eye[1], c.center[2] - c.eye[2]};
+  double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  for (double& v : f) v /= fn;
+  double r[3] = {f[1] * c.up[2] - f[2] * c.up[1], f[2] * c.up[0] - f[0] * c.up[2], f[0] * c.up[1] - f[1] * c.up[0]};
+  double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  for (double& v : r) v /= rn;
+  double u[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+  for (int a = 0; a < 3; ++a) {
+    g.eye[a] = c.eye[a];
+    g.f[a] = f[a];
+    g.r[a] = r[a];
+    g.u[a] = u[a];
+  }
+  double th = std::tan(c.fovy_deg * M_PI / 360.0);
+  g.sy = th;
+  g.sx = th * (double)c.width / (double)c.height;
+  g.W = c.width;
+  g.H = c.height;
+  return g;
+}
+
+dpr_status check_camera(const dpr_camera* c) {
+  if (!c) return fail(DPR_ERR_INVALID_ARGUMENT, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0 || (int64_t)c->width * c->height > (int64_t)1 << 30)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "camera size %dx%d invalid", c->width, c->height);
+  if (!(c->fovy_deg > 0.0 && c->fovy_deg < 180.0))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "fovy_deg %g outside (0, 180)", c->fovy_deg);
+  double f[3] = {c->center[0] - c->eye[0], c->center[1] - c->eye[1], c->center[2] - c->eye[2]};
+  double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fn > 0.0) || !std::isfinite(fn)) return fail(DPR_ERR_INVALID_ARGUMENT, "camera eye == center");
+  double r[3] = {f[1] * c->up[2] - f[2] * c->up[1], f[2] * c->up[0] - f[0] * c->up[2],
+                 f[0] * c->up[1] - f[1] * c->up[0]};
+  double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(rn > 1e-12 * fn)) return fail(DPR_ERR_INVALID_ARGUMENT, "camera up is parallel to the view direction");
+  return DPR_OK;
+}
+
+SceneG make_scene(const dpr_world_t* w) {
+  SceneG s{};
+  int64_t m = std::max(w->dims[0], std::max(w->dims[1], w->dims[2]));
+  for (int a = 0; a < 3; ++a) s.dims[a] = (int)w->dims[a];
+  s.h = 1.0 / (double)m;
+  s.inv_h = (double)m;
+  s.dt = (double)w->params.step_voxels * s.h;
+  s.dt_f = (float)s.dt;
+  s.density = w->density;
+  s.ert = w->params.ert_threshold >= 1.f ? 2.f : w->params.ert_threshold;
+  s.tf_lo = w->tf_lo;
+  s.tf_scale = (float)(w->ntf - 1) / (w->tf_hi - w->tf_lo);
+  s.ntf = w->ntf;
+  return s;
+}
+
+BrickG Brick::device_view(bool with_majorant) const {
+  BrickG g{};
+  g.data = blocked;
+  for (int a = 0; a < 3; ++a) {
+    g.slo[a] = (int)(olo[a] - glo[a]);
+    g.sdim[a] = sdim[a];
+    g.olo[a] = (int)olo[a];
+    g.ohi[a] = (int)ohi[a];
+    g.mdim[a] = mdim[a];
+  }
+  g.bsy = (uint32_t)kBlockVoxels * (uint32_t)bdim[0];
+  g.bsz = (uint32_t)kBlockVoxels * (uint32_t)bdim[0] * (uint32_t)bdim[1];
+  g.majorant = with_majorant ? maj : nullptr;
+  int sh = 0;
+  while ((1 << sh) < mc) ++sh;
+  g.mc_shift = sh;
+  return g;
+}
+
+dpr_status ensure_majorants(dpr_world_t* w) {
+  for (auto& b : w->bricks) {
+    if (b.maj_tf_version == w->tf_version) continue;
+    int count = b.mdim[0] * b.mdim[1] * b.mdim[2];
+    DPR_HIP(launch_majorants(b.ranges, count, w->tf_dev, w->ntf, w->tf_lo, w->tf_hi, b.maj, w->dev->stream));
+    b.maj_tf_version = w->tf_version;
+  }
+  return DPR_OK;
+}
+
+// Composite tables are cached per (frames, ids) so repeated composites of the same
+// frames (every dpr_render_frame) issue no host-to-device traffic at all.
+dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
+                      const std::vector<int32_t>& ids, CompTable** out) {
+  const size_t k = rgba.size();
+  std::vector<uint64_t> key;
+  key.reserve(3 * k);
+  for (size_t i = 0; i < k; ++i) {
+    key.push_back((uint64_t)(uintptr_t)rgba[i]);
+    key.push_back((uint64_t)(uintptr_t)depth[i]);
+    key.push_back((uint64_t)(uint32_t)ids[i]);
+  }
+  auto it = dev->comp_cache.find(key);
+  if (it != dev->comp_cache.end()) {
+    it->second.last_use = ++dev->use_clock;
+    *out = it->second.dev;
+    return DPR_OK;
+  }
+  if (dev->comp_cache.size() >= 64) {  // evict the least recently used table
+    auto victim = dev->comp_cache.begin();
+    for (auto j = dev->comp_cache.begin(); j != dev->comp_cache.end(); ++j)
+      if (j->second.last_use < victim->second.last_use) victim = j;
+    DPR_HIP(hipStreamSynchronize(dev->stream));
+    dev_free(victim->second.dev);
+    (void)hipHostFree(victim->second.host);
+    dev->comp_cache.erase(victim);
+  }
+  CompEntry e;
+  DPR_HIP(hipHostMalloc((void**)&e.host, sizeof(CompTable), hipHostMallocDefault));
+  memset(e.host, 0, sizeof(CompTable));
+  std::vector<int> order(k);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return ids[a] < ids[b]; });
+  for (size_t r = 0; r < k; ++r) e.host->idrank[order[r]] = (int)r;
+  for (size_t i = 0; i < k; ++i) {
+    e.host->rgba[i] = rgba[i];
+    e.host->depth[i] = depth[i];
+  }
+  dpr_status st = dev_alloc((void**)&e.dev, sizeof(CompTable), "composite table");
+  if (st != DPR_OK) {
+    (void)hipHostFree(e.host);
+    return st;
+  }
+  hipError_t he = hipMemcpyAsync(e.dev, e.host, sizeof(CompTable), hipMemcpyHostToDevice, dev->stream);
+  if (he != hipSuccess) {
+    dev_free(e.dev);
+    (void)hipHostFree(e.host);
+    return hip_fail(he, "hipMemcpyAsync(composite table)");
+  }
+  e.last_use = ++dev->use_clock;
+  dev->comp_cache[key] = e;
+  *out = e.dev;
+  return DPR_OK;
+}
+
+dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out) {
+  if (!dev || !parts || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite: NULL argument");
+  if (k < 1 || k > kMaxFrags) return fail(DPR_ERR_UNSUPPORTED, "dpr_composite: k=%d outside [1, %d]", k, kMaxFrags);
+  std::vector<const float4*> rg(k);
+  std::vector<const float*> dp(k);
+  std::vector<int32_t> id(k);
+  for (int i = 0; i < k; ++i) {
+    const dpr_frame f = parts[i];
+    if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite: part %d is NULL", i);
+    if (f->dev != dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite: part %d belongs to another device", i);
+    if (f->w != out->w || f->h != out->h)
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite: part %d is %dx%d, out is %dx%d", i, f->w, f->h, out->w,
+                  out->h);
+    if (f->rgba == out->rgba || f->depth == out->depth)
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite: out aliases part %d", i);
+    rg[i] = (const float4*)f->rgba;
+    dp[i] = f->depth;
+    id[i] = ids ? ids[i] : i;
+  }
+  std::vector<int32_t> sorted = id;
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite: fragment ids must be distinct");
+  CompTable* tab = nullptr;
+  dpr_status st = comp_table(dev, rg, dp, id, &tab);
+  if (st != DPR_OK) return st;
+  DPR_HIP(launch_composite(tab, k, out->w * out->h, (float4*)out->rgba, out->depth, dev->stream));
+  return DPR_OK;
+}
+
+}  // namespace dpr
+
+using namespace dpr;
+
+// ==================================================================== C ABI
+extern "C" {
+
+const char* dpr_last_error(void) { return g_last_error.c_str(); }
+const char* dpr_version(void) { return "dpr 0.1 gfx950"; }
+
+// ---------------------------------------------------------------- device
+dpr_status dpr_device_create(int hip_device, void* hip_stream, dpr_device* out) {
+  if (!out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_device_create: out is NULL");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0)
+    return fail(DPR_ERR_DEVICE, "dpr_device_create: no HIP device visible (%s)",
+                e != hipSuccess ? hipGetErrorString(e) : "count 0");
+  if (hip_device < 0 || hip_device >= n)
+    return fail(DPR_ERR_DEVICE, "dpr_device_create: device %d not in [0, %d)", hip_device, n);
+  DPR_HIP(hipSetDevice(hip_device));
+  hipDeviceProp_t prop;
+  DPR_HIP(hipGetDeviceProperties(&prop, hip_device));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(DPR_ERR_UNSUPPORTED, "dpr_device_create: built for gfx950, device is %s", prop.gcnArchName);
+  auto* d = new dpr_device_t;
+  d->dev = hip_device;
+  d->stream = (hipStream_t)hip_stream;
+  d->cu_count = prop.multiProcessorCount;
+  d->wave_size = prop.warpSize;
+  *out = d;
+  return DPR_OK;
+}
+
+dpr_status dpr_device_set_stream(dpr_device d, void* hip_stream) {
+  if (!d) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_device_set_stream: NULL device");
+  d->stream = (hipStream_t)hip_stream;
+  return DPR_OK;
+}
+
+dpr_status dpr_device_sync(dpr_device d) {
+  if (!d) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_device_sync: NULL device");
+  DPR_HIP(hipStreamSynchronize(d->stream));
+  DPR_HIP(hipGetLastError());
+  return DPR_OK;
+}
+
+dpr_status dpr_device_info(dpr_device d, int32_t* cu, int32_t* ws) {
+  if (!d) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_device_info: NULL device");
+  if (cu) *cu = d->cu_count;
+  if (ws) *ws = d->wave_size;
+  return DPR_OK;
+}
+
+void dpr_device_release(dpr_device d) {
+  if (!d) return;
+  (void)hipStreamSynchronize(d->stream);
+  for (auto& kv : d->comp_cache) {
+    dev_free(kv.second.dev);
+    (void)hipHostFree(kv.second.host);
+  }
+  delete d;
+}
+
+// ---------------------------------------------------------------- world
+dpr_status dpr_world_create(dpr_device d, const int64_t dims[3], dpr_world* out) {
+  if (!d || !dims || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_create: NULL argument");
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 2 || dims[a] > (1 << 20))
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_create: dims[%d]=%lld outside [2, 2^20]", a,
+                  (long long)dims[a]);
+  auto* w = new dpr_world_t;
+  w->dev = d;
+  for (int a = 0; a < 3; ++a) w->dims[a] = dims[a];
+  *out = w;
+  return DPR_OK;
+}
+
+void dpr_world_release(dpr_world w) {
+  if (!w) return;
+  (void)hipStreamSynchronize(w->dev->stream);
+  for (auto& b : w->bricks) {
+    dev_free(b.linear);
+    dev_free(b.blocked);
+    dev_free(b.ranges);
+    dev_free(b.maj);
+  }
+  for (auto f : w->partials) dpr_frame_release(f);
+  if (w->batch) batch_state_free(w->batch);
+  dev_free(w->tf_dev);
+  delete w;
+}
+
+dpr_status dpr_world_add_brick(dpr_world w, const void* voxels, dpr_dtype dtype, int on_device,
+                               const int64_t lo[3], const int64_t hi[3], const int32_t glo[3], const int32_t ghi[3],
+                               int32_t* brick_id) {
+  if (!w || !voxels || !lo || !hi || !glo || !ghi || !brick_id)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_add_brick: NULL argument");
+  if (dtype != DPR_F32 && dtype != DPR_F16)
+    return fail(DPR_ERR_UNSUPPORTED, "dpr_world_add_brick: dtype %d is neither DPR_F32 nor DPR_F16", (int)dtype);
+  Brick b{};
+  uint64_t n = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (!(0 <= lo[a] && lo[a] < hi[a] && hi[a] <= w->dims[a]))
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_add_brick: owned box axis %d [%lld, %lld) outside [0, %lld)",
+                  a, (long long)lo[a], (long long)hi[a], (long long)w->dims[a]);
+    if (glo[a] < 0 || ghi[a] < 0 || lo[a] - glo[a] < 0 || hi[a] + ghi[a] > w->dims[a])
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_add_brick: ghost layers on axis %d leave the domain", a);
+    b.olo[a] = lo[a];
+    b.ohi[a] = hi[a];
+    b.glo[a] = glo[a];
+    b.ghi[a] = ghi[a];
+    b.sdim[a] = (int)(hi[a] - lo[a] + glo[a] + ghi[a]);
+    if (b.sdim[a] < 2)
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_add_brick: stored extent %d on axis %d < 2", b.sdim[a], a);
+    b.bdim[a] = (b.sdim[a] + 7) / 8;
+    n *= (uint64_t)b.sdim[a];
+  }
+  uint64_t blocked = (uint64_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels;
+  if (blocked > 0xFFFFFFFFull)
+    return fail(DPR_ERR_UNSUPPORTED, "dpr_world_add_brick: brick of %llu blocked voxels exceeds 2^32",
+                (unsigned long long)blocked);
+  b.dtype = dtype;
+  size_t bytes = n * b.elem();
+  dpr_status st = dev_alloc(&b.linear, bytes, "brick voxels");
+  if (st != DPR_OK) return st;
+  hipError_t e = hipMemcpyAsync(b.linear, voxels, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                w->dev->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(w->dev->stream);
+  if (e != hipSuccess) {
+    dev_free(b.linear);
+    return hip_fail(e, "dpr_world_add_brick: copy");
+  }
+  w->bricks.push_back(b);
+  w->committed = false;
+  *brick_id = (int32_t)w->bricks.size() - 1;
+  return DPR_OK;
+}
+
+// Host-only partition check (no device call): disjoint owned boxes, ghost layers on
+// every owned face interior to the domain, optional tiling (DPR_REQUIRE_TILING=1).
+static dpr_status check_partition_arrays(const int64_t dims[3], int32_t n, const int64_t* lo, const int64_t* hi,
+                                         const int32_t* glo, const int32_t* ghi) {
+  if (n <= 0) return fail(DPR_ERR_INVALID_STATE, "partition: no bricks");
+  for (int32_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) {
+      const int64_t l = lo[3 * i + a], h = hi[3 * i + a];
+      if (!(0 <= l && l < h && h <= dims[a]))
+        return fail(DPR_ERR_INVALID_ARGUMENT, "partition: brick %d axis %d owned [%lld, %lld) outside [0, %lld)", i,
+                    a, (long long)l, (long long)h, (long long)dims[a]);
+      if (glo[3 * i + a] < 0 || ghi[3 * i + a] < 0 || l - glo[3 * i + a] < 0 || h + ghi[3 * i + a] > dims[a])
+        return fail(DPR_ERR_INVALID_ARGUMENT, "partition: brick %d ghost layers on axis %d leave the domain", i, a);
+      if (l > 0 && glo[3 * i + a] < 1)
+        return fail(DPR_ERR_INVALID_ARGUMENT,
+                    "partition: brick %d has no ghost layer on its interior low face of axis %d", i, a);
+      if (h < dims[a] && ghi[3 * i + a] < 1)
+        return fail(DPR_ERR_INVALID_ARGUMENT,
+                    "partition: brick %d has no ghost layer on its interior high face of axis %d", i, a);
+    }
+    for (int32_t j = i + 1; j < n; ++j) {
+      bool overlap = true;
+      for (int a = 0; a < 3; ++a) overlap &= lo[3 * i + a] < hi[3 * j + a] && lo[3 * j + a] < hi[3 * i + a];
+      if (overlap) return fail(DPR_ERR_INVALID_ARGUMENT, "partition: owned boxes of bricks %d and %d overlap", i, j);
+    }
+  }
+  const char* t = getenv("DPR_REQUIRE_TILING");
+  if (t && t[0] == '1') {
+    long double vol = 0;
+    for (int32_t i = 0; i < n; ++i)
+      vol += (long double)(hi[3 * i] - lo[3 * i]) * (hi[3 * i + 1] - lo[3 * i + 1]) * (hi[3 * i + 2] - lo[3 * i + 2]);
+    if (vol != (long double)dims[0] * dims[1] * dims[2])
+      return fail(DPR_ERR_INVALID_ARGUMENT, "partition: bricks do not tile the global domain");
+  }
+  return DPR_OK;
+}
+
+static dpr_status check_partition(const dpr_world_t* w) {
+  const auto& B = w->bricks;
+  if (B.empty()) return fail(DPR_ERR_INVALID_STATE, "dpr_world_commit: world has no bricks");
+  std::vector<int64_t> lo, hi;
+  std::vector<int32_t> glo, ghi;
+  for (const auto& b : B)
+    for (int a = 0; a < 3; ++a) {
+      lo.push_back(b.olo[a]);
+      hi.push_back(b.ohi[a]);
+      glo.push_back(b.glo[a]);
+      ghi.push_back(b.ghi[a]);
+    }
+  return check_partition_arrays(w->dims, (int32_t)B.size(), lo.data(), hi.data(), glo.data(), ghi.data());
+}
+
+dpr_status dpr_check_partition(const int64_t dims[3], int32_t n, const int64_t* lo, const int64_t* hi,
+                               const int32_t* glo, const int32_t* ghi) {
+  if (!dims || !lo || !hi || !glo || !ghi) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_check_partition: NULL argument");
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 2) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_check_partition: dims[%d] < 2", a);
+  return check_partition_arrays(dims, n, lo, hi, glo, ghi);
+}
+
+dpr_status dpr_check_camera(const dpr_camera* c) { return check_camera(c); }
+
+dpr_status dpr_world_commit(dpr_world w) {
+  if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_commit: NULL world");
+  dpr_status st = check_partition(w);
+  if (st != DPR_OK) return st;
+  const int mc = w->params.macrocell_cells;
+  for (auto& b : w->bricks) {
+    if (!b.blocked) {
+      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.elem();
+      st = dev_alloc(&b.blocked, bytes, "blocked brick");
+      if (st != DPR_OK) return st;
+    }
+    DPR_HIP(launch_relayout(b.linear, b.blocked, (int)b.elem(), b.sdim[0], b.sdim[1], b.sdim[2], b.bdim[0],
+                            b.bdim[1], b.bdim[2], w->dev->stream));
+    int md[3];
+    for (int a = 0; a < 3; ++a) md[a] = (int)((b.ohi[a] - b.olo[a] + mc - 1) / mc);
+    if (!b.ranges || b.mc != mc || md[0] != b.mdim[0] || md[1] != b.mdim[1] || md[2] != b.mdim[2]) {
+      dev_free(b.ranges);
+      dev_free(b.maj);
+      b.ranges = nullptr;
+      b.maj = nullptr;
+      size_t cnt = (size_t)md[0] * md[1] * md[2];
+      st = dev_alloc((void**)&b.ranges, cnt * sizeof(float2), "macrocell ranges");
+      if (st != DPR_OK) return st;
+      st = dev_alloc((void**)&b.maj, cnt * sizeof(float), "macrocell majorants");
+      if (st != DPR_OK) return st;
+    }
+    for (int a = 0; a < 3; ++a) b.mdim[a] = md[a];
+    b.mc = mc;
+    b.maj_tf_version = 0;
+    BrickG g = b.device_view(false);
+    DPR_HIP(launch_macrocells(g, b.dtype == DPR_F16, mc, b.ranges, w->dev->stream));
+  }
+  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  w->committed = true;
+  return DPR_OK;
+}
+
+dpr_status dpr_world_brick_count(dpr_world w, int32_t* n) {
+  if (!w || !n) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_count: NULL argument");
+  *n = (int32_t)w->bricks.size();
+  return DPR_OK;
+}
+
+dpr_status dpr_world_brick_macrocells(dpr_world w, int32_t id, int32_t md[3], float* ranges, float* maj,
+                                      size_t capacity) {
+  if (!w || !md) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_macrocells: NULL argument");
+  if (!w->committed) return fail(DPR_ERR_INVALID_STATE, "dpr_world_brick_macrocells: world not committed");
+  if (id < 0 || id >= (int)w->bricks.size())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_macrocells: brick %d does not exist", id);
+  Brick& b = w->bricks[id];
+  size_t cnt = (size_t)b.mdim[0] * b.mdim[1] * b.mdim[2];
+  if ((ranges || maj) && capacity < cnt)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_macrocells: capacity %zu < %zu", capacity, cnt);
+  if (maj) {
+    if (!w->tf_set) return fail(DPR_ERR_INVALID_STATE, "dpr_world_brick_macrocells: no transfer function set");
+    dpr_status st = ensure_majorants(w);
+    if (st != DPR_OK) return st;
+  }
+  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  if (ranges) DPR_HIP(hipMemcpy(ranges, b.ranges, cnt * sizeof(float2), hipMemcpyDeviceToHost));
+  if (maj) DPR_HIP(hipMemcpy(maj, b.maj, cnt * sizeof(float), hipMemcpyDeviceToHost));
+  for (int a = 0; a < 3; ++a) md[a] = b.mdim[a];
+  return DPR_OK;
+}
+
+dpr_status dpr_set_transfer_function(dpr_world w, const float* rgba, int32_t n, float lo, float hi, float density) {
+  if (!w || !rgba) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: NULL argument");
+  if (n < 2 || n > kMaxTF) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: n_entries %d", n);
+  if (!(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: value range [%g, %g]", lo, hi);
+  if (!(density >= 0.f) || !std::isfinite(density))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: density %g", density);
+  for (int i = 0; i < 4 * n; ++i)
+    if (!(rgba[i] >= 0.f) || !std::isfinite(rgba[i]))
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: entry %d is negative or not finite", i / 4);
+  if (w->ntf != n) {
+    dev_free(w->tf_dev);
+    w->tf_dev = nullptr;
+    w->ntf = 0;
+    dpr_status st = dev_alloc((void**)&w->tf_dev, (size_t)n * sizeof(float4), "transfer function");
+    if (st != DPR_OK) return st;
+    w->ntf = n;
+  }
+  DPR_HIP(hipMemcpyAsync(w->tf_dev, rgba, (size_t)n * sizeof(float4), hipMemcpyHostToDevice, w->dev->stream));
+  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  w->tf_lo = lo;
+  w->tf_hi = hi;
+  w->density = density;
+  w->tf_set = true;
+  ++w->tf_version;
+  return DPR_OK;
+}
+
+dpr_status dpr_set_camera(dpr_world w, const dpr_camera* c) {
+  if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_camera: NULL world");
+  dpr_status st = check_camera(c);
+  if (st != DPR_OK) return st;
+  w->cam = *c;
+  w->cam_set = true;
+  return DPR_OK;
+}
+
+dpr_status dpr_set_render_params(dpr_world w, const dpr_render_params* p) {
+  if (!w || !p) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_render_params: NULL argument");
+  if (!(p->step_voxels > 0.f && p->step_voxels <= 1.f))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_render_params: step_voxels %g outside (0, 1]", p->step_voxels);
+  if (!(p->ert_threshold > 0.f) || std::isnan(p->ert_threshold))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_render_params: ert_threshold %g", p->ert_threshold);
+  int mc = p->macrocell_cells;
+  if (mc < 2 || mc > 64 || (mc & (mc - 1)))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_render_params: macrocell_cells %d not a power of two in [2, 64]",
+                mc);
+  if (mc != w->params.macrocell_cells) w->committed = false;
+  w->params = *p;
+  return DPR_OK;
+}
+
+// ---------------------------------------------------------------- frames
+dpr_status dpr_frame_create(dpr_device d, int32_t wd, int32_t ht, dpr_frame* out) {
+  if (!d || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_create: NULL argument");
+  if (wd <= 0 || ht <= 0 || (int64_t)wd * ht > (int64_t)1 << 30)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_create: size %dx%d", wd, ht);
+  auto* f = new dpr_frame_t;
+  f->dev = d;
+  f->w = wd;
+  f->h = ht;
+  f->owned = true;
+  size_t px = (size_t)wd * ht;
+  dpr_status st = dev_alloc((void**)&f->rgba, px * 16, "frame rgba");
+  if (st == DPR_OK) st = dev_alloc((void**)&f->depth, px * 4, "frame depth");
+  if (st != DPR_OK) {
+    dev_free(f->rgba);
+    delete f;
+    return st;
+  }
+  *out = f;
+  return DPR_OK;
+}
+
+dpr_status dpr_frame_wrap(dpr_device d, int32_t wd, int32_t ht, float* rgba, float* depth, dpr_frame* out) {
+  if (!d || !out || !rgba || !depth) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_wrap: NULL argument");
+  if (wd <= 0 || ht <= 0 || (int64_t)wd * ht > (int64_t)1 << 30)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_wrap: size %dx%d", wd, ht);
+  if (((uintptr_t)rgba & 15) || ((uintptr_t)depth & 3))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_wrap: rgba must be 16-byte and depth 4-byte aligned");
+  auto* f = new dpr_frame_t;
+  f->dev = d;
+  f->w = wd;
+  f->h = ht;
+  f->rgba = rgba;
+  f->depth = depth;
+  f->owned = false;
+  *out = f;
+  return DPR_OK;
+}
+
+dpr_status dpr_frame_attach_counts(dpr_frame f, int32_t* counts) {
+  if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_attach_counts: NULL frame");
+  f->counts = counts;
+  return DPR_OK;
+}
+
+dpr_status dpr_frame_map(dpr_frame f, const float** rgba, const float** depth) {
+  if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_map: NULL frame");
+  DPR_HIP(hipStreamSynchronize(f->dev->stream));
+  DPR_HIP(hipGetLastError());
+  if (rgba) *rgba = f->rgba;
+  if (depth) *depth = f->depth;
+  return DPR_OK;
+}
+
+dpr_status dpr_frame_unmap(dpr_frame f) {
+  if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_unmap: NULL frame");
+  return DPR_OK;
+}
+
+dpr_status dpr_frame_read(dpr_frame f, float* rgba, float* depth) {
+  if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_frame_read: NULL frame");
+  DPR_HIP(hipStreamSynchronize(f->dev->stream));
+  size_t px = (size_t)f->w * f->h;
+  if (rgba) DPR_HIP(hipMemcpy(rgba, f->rgba, px * 16, hipMemcpyDeviceToHost));
+  if (depth) DPR_HIP(hipMemcpy(depth, f->depth, px * 4, hipMemcpyDeviceToHost));
+  return DPR_OK;
+}
+
+void dpr_frame_release(dpr_frame f) {
+  if (!f) return;
+  if (f->owned) {
+    (void)hipStreamSynchronize(f->dev->stream);
+    dev_free(f->rgba);
+    dev_free(f->depth);
+  }
+  delete f;
+}
+
+// ---------------------------------------------------------------- render / composite
+static dpr_status check_renderable(dpr_world w, const char* who) {
+  if (!w->committed) return fail(DPR_ERR_INVALID_STATE, "%s: world not committed", who);
+  if (!w->tf_set) return fail(DPR_ERR_INVALID_STATE, "%s: no transfer function set", who);
+  if (!w->cam_set) return fail(DPR_ERR_INVALID_STATE, "%s: no camera set", who);
+  return DPR_OK;
+}
+
+static dpr_status render_brick(dpr_world w, int id, dpr_frame out) {
+  const Brick& b = w->bricks[id];
+  const bool skip = !(w->params.flags & DPR_FLAG_NO_SKIP);
+  SceneG sc = make_scene(w);
+  CamG cam = make_cam(w->cam);
+  DPR_HIP(launch_march(sc, b.device_view(skip), cam, w->tf_dev, b.dtype == DPR_F16, skip, (float4*)out->rgba,
+                       out->depth, out->counts, w->dev->stream));
+  return DPR_OK;
+}
+
+dpr_status dpr_render_partial(dpr_world w, int32_t id, dpr_frame out) {
+  if (!w || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_partial: NULL argument");
+  dpr_status st = check_renderable(w, "dpr_render_partial");
+  if (st != DPR_OK) return st;
+  if (id < 0 || id >= (int)w->bricks.size())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_partial: brick %d does not exist", id);
+  if (out->w != w->cam.width || out->h != w->cam.height)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_partial: frame %dx%d != camera %dx%d", out->w, out->h,
+                w->cam.width, w->cam.height);
+  if (out->dev != w->dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_partial: frame of another device");
+  st = ensure_majorants(w);
+  if (st != DPR_OK) return st;
+  return render_brick(w, id, out);
+}
+
+dpr_status dpr_composite(dpr_device d, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out) {
+  return composite_frames(d, parts, ids, k, out);
+}
+
+dpr_status dpr_render_frame(dpr_world w, dpr_frame out) {
+  if (!w || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_frame: NULL argument");
+  dpr_status st = check_renderable(w, "dpr_render_frame");
+  if (st != DPR_OK) return st;
+  if (out->w != w->cam.width || out->h != w->cam.height)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_frame: frame %dx%d != camera %dx%d", out->w, out->h,
+                w->cam.width, w->cam.height);
+  const int K = (int)w->bricks.size();
+  if (K > kMaxFrags) return fail(DPR_ERR_UNSUPPORTED, "dpr_render_frame: %d bricks > %d", K, kMaxFrags);
+  bool resize = (int)w->partials.size() != K;
+  for (auto f : w->partials) resize |= f->w != out->w || f->h != out->h;
+  if (resize) {
+    for (auto f : w->partials) dpr_frame_release(f);
+    w->partials.clear();
+    for (int i = 0; i < K; ++i) {
+      dpr_frame f = nullptr;
+      st = dpr_frame_create(w->dev, out->w, out->h, &f);
+      if (st != DPR_OK) return st;
+      w->partials.push_back(f);
+    }
+  }
+  st = ensure_majorants(w);
+  if (st != DPR_OK) return st;
+  for (int i = 0; i < K; ++i) {
+    st = render_brick(w, i, w->partials[i]);
+    if (st != DPR_OK) return st;
+  }
+  std::vector<int32_t> ids(K);
+  std::iota(ids.begin(), ids.end(), 0);
+  return composite_frames(w->dev, w->partials.data(), ids.data(), K, out);
+}
+
+}  // extern "C"

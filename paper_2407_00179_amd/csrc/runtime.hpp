@@ -1,0 +1,117 @@
+// Host-side runtime objects behind the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/dpr.h"
+#include "kernels.h"
+
+namespace dpr {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+dpr_status fail(dpr_status st, const char* fmt, ...);
+dpr_status hip_fail(hipError_t e, const char* what);
+bool log_enabled();
+
+#define DPR_HIP(call)                                          \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return ::dpr::hip_fail(e_, #call);   \
+  } while (0)
+
+// Device allocation with optional fault injection (DPR_FAULT_INJECT=alloc:N makes
+// the N-th allocation of the process fail with DPR_ERR_OUT_OF_MEMORY).
+dpr_status dev_alloc(void** p, size_t bytes, const char* what);
+void dev_free(void* p);
+
+struct CompEntry {
+  CompTable* dev = nullptr;
+  CompTable* host = nullptr;   // pinned; the async upload reads it
+  uint64_t last_use = 0;
+};
+
+}  // namespace dpr
+
+struct dpr_device_t {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  int cu_count = 0;
+  int wave_size = 64;
+  // composite tables keyed by (rgba ptr, depth ptr, id) of every part
+  std::map<std::vector<uint64_t>, dpr::CompEntry> comp_cache;
+  uint64_t use_clock = 0;
+};
+
+struct dpr_frame_t {
+  dpr_device dev = nullptr;
+  int w = 0, h = 0;
+  float* rgba = nullptr;
+  float* depth = nullptr;
+  int* counts = nullptr;
+  bool owned = false;
+};
+
+namespace dpr {
+
+struct Brick {
+  int64_t olo[3], ohi[3];
+  int32_t glo[3], ghi[3];
+  int sdim[3];
+  dpr_dtype dtype;
+  void* linear = nullptr;     // stored region as given (x fastest)
+  void* blocked = nullptr;    // 8^3-blocked copy used by the kernels
+  int bdim[3] = {0, 0, 0};
+  float2* ranges = nullptr;   // macrocell min/max
+  float* maj = nullptr;       // macrocell majorant
+  int mdim[3] = {0, 0, 0};
+  int mc = 0;
+  uint64_t maj_tf_version = 0;
+  size_t elem() const { return dtype == DPR_F16 ? 2 : 4; }
+  BrickG device_view(bool with_majorant) const;
+};
+
+struct BatchState;  // persistent batched renderer (k_batch.hip)
+void batch_state_free(BatchState*);
+
+}  // namespace dpr
+
+struct dpr_world_t {
+  dpr_device dev = nullptr;
+  int64_t dims[3] = {0, 0, 0};
+  std::vector<dpr::Brick> bricks;
+  bool committed = false;
+  // transfer function
+  float4* tf_dev = nullptr;
+  int ntf = 0;
+  float tf_lo = 0.f, tf_hi = 1.f, density = 0.f;
+  bool tf_set = false;
+  uint64_t tf_version = 0;
+  // camera and parameters
+  dpr_camera cam{};
+  bool cam_set = false;
+  dpr_render_params params{0.5f, 0.99f, 16, 0u};
+  // partial frames of dpr_render_frame (one per brick)
+  std::vector<dpr_frame> partials;
+  dpr::BatchState* batch = nullptr;
+  int batch_tile_w = 16, batch_tile_h = 16;
+};
+
+namespace dpr {
+
+CamG make_cam(const dpr_camera& c);
+SceneG make_scene(const dpr_world_t* w);
+dpr_status check_camera(const dpr_camera* c);
+dpr_status ensure_majorants(dpr_world_t* w);
+dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out);
+dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
+                      const std::vector<int32_t>& ids, CompTable** out);
+
+}  // namespace dpr

@@ -1,0 +1,248 @@
+"""GPU parity of the per-brick ray march, macrocells and render_frame against the oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import RenderParams
+from synth import (Camera, even_split, extract_brick, get_config, kd_split, make_blobs, make_tf, make_volume_small,
+                   orbit_camera, pixel_subset)
+from tests.gpu_util import TOL_F16, TOL_F32, check_bracketed, frame_np, log, make_world, oracle_brick
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dpr():
+    import paper_2407_00179_amd as m
+    return m
+
+
+def _small_case(dims=(40, 36, 28), seed=3, nb=6, dtype=np.float32):
+    vol = make_volume_small(dims, make_blobs(dims, seed, nb, (0.08, 0.25)), seed + 1, 0.02, dtype)
+    return vol, make_tf(2001)
+
+
+@pytest.mark.parametrize("ert", [1.0, 0.99])
+@pytest.mark.parametrize("size", [(64, 48), (37, 29), (1, 1), (130, 17)])
+def test_single_brick_full_frame(gpu_lib, dpr, ert, size):
+    dims = (40, 36, 28)
+    vol, tf = _small_case(dims)
+    prm = RenderParams(0.5, ert, 20.0)
+    cam = orbit_camera(dims, *size)
+    log(f"single brick {dims} image {size} ert {ert}")
+    w = make_world(dpr, gpu_lib, vol, dims, [((0, 0, 0), dims)], tf, prm, cam)
+    fr = dpr.Frame(gpu_lib, *size, counts=True)
+    w.render_partial(0, fr)
+    rgba, depth, n = frame_np(fr)
+    py, px = np.mgrid[0:size[1], 0:size[0]]
+    px, py = px.ravel(), py.ravel()
+    check_bracketed(rgba, depth, n, lambda th: oracle_brick(vol, dims, (0, 0, 0), dims, tf, prm, cam, px, py, th),
+                    ert, TOL_F32, f"1 brick {size}")
+    w.release()
+
+
+def test_cfg1_full(gpu_lib, dpr):
+    cfg = get_config("cfg1")
+    dims = cfg.dims
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+    tf = make_tf(cfg.seeds["tf"])
+    prm = RenderParams(cfg.step_voxels, cfg.ert, cfg.density)
+    cam = orbit_camera(dims, *cfg.image)
+    log("cfg1 64^3 256x256")
+    w = make_world(dpr, gpu_lib, vol, dims, [((0, 0, 0), dims)], tf, prm, cam)
+    fr = dpr.Frame(gpu_lib, *cfg.image, counts=True)
+    w.render_partial(0, fr)
+    rgba, depth, n = frame_np(fr)
+    py, px = np.mgrid[0:cfg.image[1], 0:cfg.image[0]]
+    px, py = px.ravel(), py.ravel()
+    check_bracketed(rgba, depth, n, lambda th: oracle_brick(vol, dims, (0, 0, 0), dims, tf, prm, cam, px, py, th),
+                    cfg.ert, TOL_F32, "cfg1")
+    assert rgba[:, 3].max() > 0.9
+    w.release()
+
+
+@pytest.mark.parametrize("split", ["2x2x2", "kd7", "3x2x1"])
+@pytest.mark.parametrize("ert", [1.0, 0.99])
+def test_bricks_partials_and_frame(gpu_lib, dpr, split, ert):
+    dims = (48, 40, 33)
+    vol, tf = _small_case(dims, seed=11)
+    prm = RenderParams(0.5, ert, 25.0)
+    cam = orbit_camera(dims, 72, 61)
+    boxes = (kd_split(dims, 7, seed=3, max_ratio=6.0) if split == "kd7"
+             else even_split(dims, tuple(int(c) for c in split.split("x"))))
+    log(f"bricks {split} ert {ert}")
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=8)
+    py, px = np.mgrid[0:cam.height, 0:cam.width]
+    px, py = px.ravel(), py.ravel()
+    parts = []
+    for i, (lo, hi) in enumerate(boxes):
+        fr = dpr.Frame(gpu_lib, cam.width, cam.height, counts=True)
+        w.render_partial(i, fr)
+        rgba, depth, n = frame_np(fr)
+        check_bracketed(rgba, depth, n, lambda th: oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, th),
+                        ert, TOL_F32, f"brick {i}")
+        parts.append(fr)
+    out = dpr.Frame(gpu_lib, cam.width, cam.height)
+    w.render_frame(out)
+    got, gz, _ = frame_np(out)
+    # the composite of the GPU's own partials through dpr_composite matches render_frame bitwise
+    out2 = dpr.Frame(gpu_lib, cam.width, cam.height)
+    dpr.composite(gpu_lib, parts[::-1], out2, ids=list(range(len(parts)))[::-1])
+    got2, gz2, _ = frame_np(out2)
+    assert np.array_equal(got, got2) and np.array_equal(gz, gz2)
+    # versus the oracle's composite of the oracle's partials
+    orc = [oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py) for lo, hi in boxes]
+    want, wz = oracle.composite(np.stack([o[0] for o in orc]), np.stack([o[1] for o in orc]))
+    tol = TOL_F32 if ert >= 1.0 else 2 * TOL_F32 + 0.0
+    if ert >= 1.0:
+        err = np.max(np.abs(got - want))
+        assert err <= TOL_F32, err
+        # split invariant on the GPU: composite == unsplit render (ERT off)
+        wu = make_world(dpr, gpu_lib, vol, dims, [((0, 0, 0), dims)], tf, prm, cam)
+        un = dpr.Frame(gpu_lib, cam.width, cam.height)
+        wu.render_partial(0, un)
+        gu, guz, _ = frame_np(un)
+        inv = np.max(np.abs(got - gu))
+        log(f"  composite vs oracle {err:.3e}; GPU split invariant |composite - unsplit| = {inv:.3e}")
+        assert inv <= TOL_F32
+        fin = np.isfinite(guz)
+        assert np.array_equal(np.isfinite(gz), fin) and np.allclose(gz[fin], guz[fin], rtol=3e-7, atol=0)
+        wu.release()
+    else:
+        # per-brick ERT: composite within 2 (1 - theta) of the oracle's composite
+        # and each partial already matched its bracket
+        err = np.max(np.abs(got - want))
+        log(f"  composite (ERT {ert}) vs oracle composite {err:.3e}")
+        assert err <= 2 * (1 - ert) + tol
+    w.release()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_skip_is_bitwise_neutral(gpu_lib, dpr, dtype):
+    dims = (64, 56, 48)
+    vol, tf = _small_case(dims, seed=21, nb=4, dtype=dtype)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 96, 80)
+    boxes = even_split(dims, (2, 1, 2))
+    res = []
+    for flags in (0, 1):
+        w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, flags=flags)
+        out = dpr.Frame(gpu_lib, cam.width, cam.height, counts=True)
+        w.render_partial(1, out)
+        res.append(frame_np(out))
+        w.release()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+def test_macrocells_and_majorants_bitwise(gpu_lib, dpr):
+    dims = (70, 45, 38)
+    vol, tf = _small_case(dims, seed=31, nb=5)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 16, 16)
+    boxes = kd_split(dims, 5, seed=9, max_ratio=8.0)
+    for mc in (16, 4):
+        w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=mc)
+        for i, (lo, hi) in enumerate(boxes):
+            b = extract_brick(vol, dims, lo, hi)
+            want_r = oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, mc)
+            want_m = oracle.majorants(want_r, tf)
+            got_r, got_m = w.macrocells(i)
+            assert np.array_equal(got_r, want_r), (mc, i)
+            assert np.array_equal(got_m, want_m), (mc, i)
+            assert np.any(got_m == 0.0) or mc == 16
+        w.release()
+
+
+def test_f16_volume(gpu_lib, dpr):
+    dims = (50, 42, 36)
+    vol, tf = _small_case(dims, seed=41, dtype=np.float16)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 64, 64)
+    boxes = even_split(dims, (2, 2, 1))
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, on_device=True)
+    py, px = np.mgrid[0:64, 0:64]
+    px, py = px.ravel(), py.ravel()
+    for i, (lo, hi) in enumerate(boxes):
+        fr = dpr.Frame(gpu_lib, 64, 64, counts=True)
+        w.render_partial(i, fr)
+        rgba, depth, n = frame_np(fr)
+        err = check_bracketed(rgba, depth, n,
+                              lambda th: oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, th),
+                              prm.ert, TOL_F16, f"f16 brick {i}")
+        assert err <= TOL_F32   # FP16 storage, FP32 arithmetic on identical bits
+    w.release()
+
+
+def test_step_and_camera_variants(gpu_lib, dpr):
+    dims = (33, 31, 29)
+    vol, tf = _small_case(dims, seed=51)
+    cams = [Camera((0.5, 0.49, 3.1), (0.5, 0.47, 0.44), (0.0, 1.0, 0.0), 45.0, 41, 37),   # from +z
+            Camera((0.4, 0.45, 0.42), (1.5, 1.0, 0.9), (0.0, 0.0, 1.0), 90.0, 40, 30)]    # eye inside
+    for step in (1.0, 0.37, 0.25):
+        for cam in cams:
+            prm = RenderParams(step, 0.99, 30.0)
+            boxes = even_split(dims, (2, 2, 2))
+            w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=4)
+            py, px = np.mgrid[0:cam.height, 0:cam.width]
+            px, py = px.ravel(), py.ravel()
+            for i in (0, 7):
+                lo, hi = boxes[i]
+                fr = dpr.Frame(gpu_lib, cam.width, cam.height, counts=True)
+                w.render_partial(i, fr)
+                rgba, depth, n = frame_np(fr)
+                check_bracketed(rgba, depth, n,
+                                lambda th: oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, th),
+                                prm.ert, TOL_F32, f"step {step} brick {i}")
+            w.release()
+
+
+def test_cfg2_full_size_sampled(gpu_lib, dpr):
+    """512^3 FP32 split 2x2x2 (257^3 stored bricks), 1024^2: sampled pixels against
+    the oracle, the full frame against the GPU's own unsplit render (ERT off)."""
+    from synth import white_noise  # noqa: F401
+    cfg = get_config("cfg2")
+    dims = cfg.dims
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    log("cfg2: generating 512^3 volume")
+    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+    tf = make_tf(cfg.seeds["tf"])
+    cam = orbit_camera(dims, *cfg.image)
+    px, py = pixel_subset(*cfg.image, stride=32, tiles=2, tile=32, seed=7)
+    boxes = even_split(dims, cfg.parts)
+    for ert in (1.0, cfg.ert):
+        prm = RenderParams(cfg.step_voxels, ert, cfg.density)
+        log(f"cfg2 ert {ert}: building world")
+        w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam)
+        out = dpr.Frame(gpu_lib, *cfg.image)
+        w.render_frame(out)
+        got, gz, _ = frame_np(out)
+        sel = py * cfg.image[0] + px
+        orc = [oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py) for lo, hi in boxes]
+        want, wz = oracle.composite(np.stack([o[0] for o in orc]), np.stack([o[1] for o in orc]))
+        err = np.max(np.abs(got[sel] - want))
+        log(f"  cfg2 composite vs oracle on {sel.size} pixels: {err:.3e}")
+        if ert >= 1.0:
+            assert err <= TOL_F32
+            wu = make_world(dpr, gpu_lib, vol, dims, [((0, 0, 0), dims)], tf, prm, cam)
+            un = dpr.Frame(gpu_lib, *cfg.image)
+            wu.render_partial(0, un)
+            gu, _, _ = frame_np(un)
+            inv = np.max(np.abs(got - gu))
+            log(f"  cfg2 GPU split invariant (full frame): {inv:.3e}")
+            assert inv <= TOL_F32
+            wu.release()
+        else:
+            assert err <= 2 * (1 - ert) + TOL_F32
+            # per-brick partials against the bracketed oracle on the sample
+            for i in (0, 5):
+                lo, hi = boxes[i]
+                fr = dpr.Frame(gpu_lib, *cfg.image, counts=True)
+                w.render_partial(i, fr)
+                r, z, n = frame_np(fr)
+                check_bracketed(r[sel], z[sel], n[sel],
+                                lambda th: oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, th),
+                                ert, TOL_F32, f"cfg2 brick {i}")
+        w.release()
