@@ -119,7 +119,8 @@ def render_pixel(vol, stored_lo, dims, owned_lo, owned_hi, tf, params, cam, px, 
 
 
 def composite_pixel(frags):
-    """frags: list of (rgba4, depth, id).  Front-to-back over after sorting by (depth, id)."""
+    """frags: list of (rgba4, depth, id).  Front-to-back over after sorting by (depth, id);
+    alpha as 1 - prod(1 - alpha_i), the product form of the same quantity."""
     live = sorted([f for f in frags if f[1] != math.inf], key=lambda f: (f[1], f[2]))
     col = [0.0, 0.0, 0.0]
     for i, (rgba, _, _) in enumerate(live):

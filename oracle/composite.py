@@ -9,9 +9,12 @@ back, so no fixed compositing order across ranks is needed.
 Reading (C12): per pixel, take the fragments with finite depth (an empty
 fragment has depth +inf and RGBA 0); sort ascending by (depth, fragment id),
 where the id is intrinsic to the fragment (its rank / brick), not its position
-in the input list; then T = 1, C = 0 and for each fragment C += T*rgb_i,
-T *= (1 - alpha_i).  Output premultiplied (C, 1 - T); depth = min depth
-(+inf when no fragment is present).
+in the input list; then T = 1, C = 0 and for each fragment the premultiplied
+"over" acts on all four channels alike: C_rgba += T*rgba_i, T *= (1 - alpha_i).
+The output alpha sum_i T_i alpha_i equals 1 - prod_i (1 - alpha_i) in exact
+arithmetic; accumulating it like the colour makes one fragment composite to
+itself bit for bit in any precision.  Depth = min depth (+inf when no fragment
+is present).
 """
 
 from __future__ import annotations
@@ -35,7 +38,7 @@ def composite(rgba, depth, ids=None):
     ids = np.arange(K) if ids is None else np.asarray(ids)
     idk = np.broadcast_to(ids[:, None], (K, P))
     order = np.lexsort((idk, depth), axis=0)  # primary key depth, then id
-    C = np.zeros((P, 3))
+    C = np.zeros((P, 4))
     T = np.ones(P)
     cols = np.arange(P)
     for r in range(K):
@@ -43,10 +46,8 @@ def composite(rgba, depth, ids=None):
         z = depth[k, cols]
         f = rgba[k, cols]
         present = np.isfinite(z)
-        C += np.where(present[:, None], T[:, None] * f[:, :3], 0.0)
+        C += np.where(present[:, None], T[:, None] * f, 0.0)
         T = np.where(present, T * (1.0 - f[:, 3]), T)
-    out = np.empty((P, 4))
-    out[:, :3] = C
-    out[:, 3] = 1.0 - T
+    out = C
     zmin = np.min(depth, axis=0) if K else np.full(P, np.inf)
     return out.reshape(pix_shape + (4,)), zmin.reshape(pix_shape)

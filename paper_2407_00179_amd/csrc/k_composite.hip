@@ -1,5 +1,6 @@
 // Sort-last compositor: per pixel, sort the RGBA-z fragments with finite depth by
-// (depth, id rank) and composite them front to back.
+// (depth, id rank) and composite them front to back with the premultiplied "over"
+// on all four channels: C += T rgba_i, T *= 1 - alpha_i.
 //
 // One wave owns 64 consecutive pixels.  All k depths of those pixels are staged in
 // LDS with coalesced loads (4 B per fragment, the only bytes read for empty
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(64) void composite_kernel(const CompTable* __restri
     ++n;
   }
   // 4. front-to-back over, RGBA fetched for live fragments only
-  float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f;
   int i = 0;
   for (; i + 4 <= n; i += 4) {
     float4 f[4];
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(64) void composite_kernel(const CompTable* __restri
       cr = fmaf(tr, f[u].x, cr);
       cg = fmaf(tr, f[u].y, cg);
       cb = fmaf(tr, f[u].z, cb);
+      ca = fmaf(tr, f[u].w, ca);
       tr *= 1.f - f[u].w;
     }
   }
@@ -100,10 +102,11 @@ __global__ __launch_bounds__(64) void composite_kernel(const CompTable* __restri
     cr = fmaf(tr, f.x, cr);
     cg = fmaf(tr, f.y, cg);
     cb = fmaf(tr, f.z, cb);
+    ca = fmaf(tr, f.w, ca);
     tr *= 1.f - f.w;
   }
   if (live_px) {
-    out_rgba[p] = make_float4(cr, cg, cb, 1.f - tr);
+    out_rgba[p] = make_float4(cr, cg, cb, ca);
     out_depth[p] = n ? zs[lst[0][lane]][lane] : INFINITY;
   }
 }

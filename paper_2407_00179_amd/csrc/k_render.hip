@@ -2,6 +2,7 @@
 // the per-brick emission-absorption ray march, for gfx950.
 #include "device_common.h"
 #include "kernels.h"
+#include "march.h"
 
 namespace dpr {
 
@@ -90,118 +91,6 @@ __global__ __launch_bounds__(256) void majorant_kernel(const float2* __restrict_
   maj[m] = a;
 }
 
-// ------------------------------------------------------------------ ray march
-// Stage the TF as (entry, next - entry) pairs so a lookup is one FMA per channel.
-__device__ __forceinline__ void stage_tf(const float4* __restrict__ tf, int ntf, float4* base, float4* slope,
-                                         int tid, int nthreads) {
-  for (int i = tid; i < ntf; i += nthreads) {
-    float4 a = tf[i];
-    float4 b = (i + 1 < ntf) ? tf[i + 1] : a;
-    base[i] = a;
-    slope[i] = make_float4(b.x - a.x, b.y - a.y, b.z - a.z, b.w - a.w);
-  }
-}
-
-template <typename T, bool SKIP>
-__device__ __forceinline__ void march_ray(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
-                                          const float4* __restrict__ tfs, const double o[3], const double d[3],
-                                          float4& out, float& depth, int& nsamp) {
-  double lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = b.olo[a] * sc.h;
-    hi[a] = b.ohi[a] * sc.h;
-  }
-  double t_in, t_out;
-  if (!clip_box(o, d, lo, hi, t_in, t_out)) {
-    out = make_float4(0.f, 0.f, 0.f, 0.f);
-    depth = INFINITY;
-    nsamp = 0;
-    return;
-  }
-  const double dt = sc.dt;
-  const int s0 = (int)floor(t_in / dt);
-  const int s1 = (int)ceil(t_out / dt) - 1;
-  double ov[3], dv[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    ov[a] = o[a] * sc.inv_h - 0.5;
-    dv[a] = d[a] * sc.inv_h;
-  }
-  const T* vox = (const T*)b.data;
-  const double nx1 = sc.dims[0] - 1, ny1 = sc.dims[1] - 1, nz1 = sc.dims[2] - 1;
-  const float Ddt = sc.density * sc.dt_f;
-  float cr = 0.f, cg = 0.f, cb = 0.f, tr = 1.f;
-  double tau_acc = 0.0;
-  int n = 0;
-  for (int s = s0; s <= s1; ++s) {
-    const double tlo = (double)s * dt;
-    const double thi = tlo + dt;
-    float Dl = Ddt;
-    if (tlo < t_in || thi > t_out) {
-      double l = fmin(thi, t_out) - fmax(tlo, t_in);
-      if (!(l > 0.0)) continue;
-      Dl = sc.density * (float)l;
-    }
-    ++n;
-    const double tm = tlo + 0.5 * dt;
-    const double gx = fma(tm, dv[0], ov[0]);
-    const double gy = fma(tm, dv[1], ov[1]);
-    const double gz = fma(tm, dv[2], ov[2]);
-    if (SKIP) {
-      int mx = ((int)floor(gx + 0.5) - b.olo[0]) >> b.mc_shift;
-      int my = ((int)floor(gy + 0.5) - b.olo[1]) >> b.mc_shift;
-      int mz = ((int)floor(gz + 0.5) - b.olo[2]) >> b.mc_shift;
-      mx = min(max(mx, 0), b.mdim[0] - 1);
-      my = min(max(my, 0), b.mdim[1] - 1);
-      mz = min(max(mz, 0), b.mdim[2] - 1);
-      if (b.majorant[(mz * b.mdim[1] + my) * b.mdim[0] + mx] == 0.f) continue;
-    }
-    const double cx = fmin(fmax(gx, 0.0), nx1);
-    const double cy = fmin(fmax(gy, 0.0), ny1);
-    const double cz = fmin(fmax(gz, 0.0), nz1);
-    const int ix = min((int)floor(cx), sc.dims[0] - 2);
-    const int iy = min((int)floor(cy), sc.dims[1] - 2);
-    const int iz = min((int)floor(cz), sc.dims[2] - 2);
-    const float fx = (float)(cx - ix), fy = (float)(cy - iy), fz = (float)(cz - iz);
-    // commit guarantees these lie in [0, sdim - 2]; the clamp only guards memory
-    const int lx = min(max(ix - b.slo[0], 0), b.sdim[0] - 2);
-    const int ly = min(max(iy - b.slo[1], 0), b.sdim[1] - 2);
-    const int lz = min(max(iz - b.slo[2], 0), b.sdim[2] - 2);
-    const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
-    const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
-    const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
-    const float v000 = load_voxel<T>(vox, x0 + y0 + z0), v001 = load_voxel<T>(vox, x1 + y0 + z0);
-    const float v010 = load_voxel<T>(vox, x0 + y1 + z0), v011 = load_voxel<T>(vox, x1 + y1 + z0);
-    const float v100 = load_voxel<T>(vox, x0 + y0 + z1), v101 = load_voxel<T>(vox, x1 + y0 + z1);
-    const float v110 = load_voxel<T>(vox, x0 + y1 + z1), v111 = load_voxel<T>(vox, x1 + y1 + z1);
-    const float c00 = fmaf(fx, v001 - v000, v000), c01 = fmaf(fx, v011 - v010, v010);
-    const float c10 = fmaf(fx, v101 - v100, v100), c11 = fmaf(fx, v111 - v110, v110);
-    const float c0 = fmaf(fy, c01 - c00, c00), c1 = fmaf(fy, c11 - c10, c10);
-    const float v = fmaf(fz, c1 - c0, c0);
-    float x = (v - sc.tf_lo) * sc.tf_scale;
-    x = fminf(fmaxf(x, 0.f), (float)(sc.ntf - 1));
-    const int j = min((int)x, sc.ntf - 2);
-    const float w = x - (float)j;
-    const float4 tb = tfb[j], ts = tfs[j];
-    const float A = fmaf(w, ts.w, tb.w);
-    const float tau = Dl * A;
-    if (tau > 0.f) {
-      tau_acc += (double)tau;
-      const float tn = __expf(-(float)tau_acc);
-      const float wgt = tr - tn;
-      cr = fmaf(wgt, fmaf(w, ts.x, tb.x), cr);
-      cg = fmaf(wgt, fmaf(w, ts.y, tb.y), cg);
-      cb = fmaf(wgt, fmaf(w, ts.z, tb.z), cb);
-      tr = tn;
-      if (1.f - tr >= sc.ert) break;
-    }
-  }
-  out = make_float4(cr, cg, cb, 1.f - tr);
-  depth = (float)t_in;
-  nsamp = n;
-}
-
 // Plain per-brick launch: one thread per pixel, 16x16 tiles as four 8x8 waves,
 // tiles assigned so that each XCD (round-robin workgroup dispatch) walks one
 // contiguous band of the screen and keeps its part of the brick in its own L2.
@@ -225,14 +114,18 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
   if (px >= cam.W || py >= cam.H) return;
   double d[3];
   camera_ray(cam, px, py, d);
-  float4 c;
-  float z;
-  int n;
-  march_ray<T, SKIP>(sc, b, tfb, tfs, cam.eye, d, c, z, n);
+  RayState r;
   const size_t p = (size_t)py * cam.W + px;
-  out_rgba[p] = c;
-  out_depth[p] = z;
-  if (out_count) out_count[p] = n;
+  if (ray_begin(sc, b, cam.eye, d, r)) {
+    ray_advance<T, SKIP>(sc, b, tfb, tfs, r, 0x7fffffff);
+    out_rgba[p] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
+    out_depth[p] = (float)r.t_in;
+  } else {
+    r.n = 0;
+    out_rgba[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    out_depth[p] = INFINITY;
+  }
+  if (out_count) out_count[p] = r.n;
 }
 
 // ------------------------------------------------------------------ host launchers
