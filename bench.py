@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of the data-parallel brick renderer + sort-last compositor on one MI355X.
+
+Default workload (one "step" = the whole hot path once): a 512^3 FP32 blob+noise
+volume split into 2x2x2 bricks of 256^3 owned cells with one ghost layer
+(257^3 stored), rendered at 1024x1024 through one camera:
+  commit (8^3 relayout of every brick + macrocell min/max ranges)
+  -> transfer-function majorants
+  -> 8 per-brick emission-absorption ray marches (partial RGBA+depth frames)
+  -> sort-last composite of the 8 partial frames.
+value = logical samples per second (lattice segments of positive length
+processed before termination, skipped ones included), in Msamples/s.
+
+Extra sections (same JSON line): the K=128 compositor at 3840x2160, the batched
+persistent renderer against plain per-brick launches on the 27-brick 16-camera
+workload, and the backward/forward time ratio of the differentiable renderer.
+
+The CPU baseline (the FP64 oracle, not tuned) runs first, before any GPU use,
+on a bounded pixel sample of the default workload, over a fork pool of host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from synth import (even_split, extract_brick, get_config, make_blobs, make_tf,  # noqa: E402
+                   make_volume_small, orbit_camera)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # CUs x lanes x clock: lane-op slots per second (non-packed)
+OPS_PER_SAMPLE = 60              # algorithmic VALU lane-op slots per logical sample
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- CPU baseline (oracle)
+_CPU = {}
+
+
+def _cpu_worker(args):
+    import oracle
+    bricks, vol_dims, tf, prm, cam, px, py = _CPU["data"]
+    parts = []
+    samples = 0
+    for b in bricks:
+        r, z, n = oracle.render_brick(b.data, b.stored_lo, vol_dims, b.lo, b.hi, tf, prm, cam, px[args], py[args])
+        parts.append((r, z))
+        samples += int(n.sum())
+    oracle.composite(np.stack([p[0] for p in parts]), np.stack([p[1] for p in parts]))
+    return samples
+
+
+def cpu_baseline(bricks, dims, tf, prm, cam, stride, cores):
+    import oracle  # noqa: F401  (imported before forking)
+    py, px = np.mgrid[0:cam.height:stride, 0:cam.width:stride]
+    px, py = px.ravel(), py.ravel()
+    _CPU["data"] = (bricks, dims, tf, prm, cam, px, py)
+    chunks = np.array_split(np.arange(px.size), cores * 4)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        samples = sum(pool.map(_cpu_worker, chunks))
+    dt = time.perf_counter() - t0
+    return dict(value=samples / dt / 1e6, unit="Msamples/s", cores=cores, kind="oracle",
+                sample=f"every {stride}th pixel in x and y ({px.size} rays) x {len(bricks)} bricks + composite, "
+                       f"{samples} logical samples in {dt:.1f} s, FP64 numpy over a fork pool")
+
+
+# ---------------------------------------------------------------- GPU sections
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
+    dev = dpr.Device(0)
+    w = dpr.World(dev, dims)
+    prm = dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0)
+    w.set_params(prm)
+    for b in vol_bricks:
+        w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)
+    w.commit()
+    w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+    w.set_camera(cam)
+    W, H = cfg.image
+    K = len(vol_bricks)
+    parts = [dpr.Frame(dev, W, H) for _ in range(K)]
+    out = dpr.Frame(dev, W, H)
+    # logical samples of one frame (counts attached for one untimed pass)
+    total = 0
+    for i, f in enumerate(parts):
+        c = f.attach_counts()
+        w.render_partial(i, f)
+        dev.sync()
+        total += int(c.sum().item())
+        dpr.check(dpr.lib.dpr_frame_attach_counts(f.h, None))
+        f.counts = None
+
+    def step(ev=None):
+        w.commit()
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+        for i, f in enumerate(parts):
+            if ev is not None:
+                ev["march"][i][0].record()
+            w.render_partial(i, f)
+            if ev is not None:
+                ev["march"][i][1].record()
+        if ev is not None:
+            ev["comp"][0].record()
+        dpr.composite(dev, parts, out, ids=list(range(K)))
+        if ev is not None:
+            ev["comp"][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [dict(march=[_events(torch) for _ in range(K)], comp=_events(torch)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    march_ms = [e["march"][i][0].elapsed_time(e["march"][i][1]) for e in evs for i in range(K)]
+    comp_ms = [e["comp"][0].elapsed_time(e["comp"][1]) for e in evs]
+    ms_step = wall * 1e3 / args.steps
+    # compositor algorithmic bytes: all depths, RGBA of live fragments, output
+    live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
+    comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
+    res = dict(ms_per_step=ms_step, samples=total, march_ms_per_launch=float(np.mean(march_ms)),
+               march_ms_per_frame=float(np.mean(march_ms)) * K, comp_ms=float(np.mean(comp_ms)),
+               comp_bytes=comp_bytes, live_fragments=live)
+    w.release()
+    for f in parts + [out]:
+        f.release()
+    return dev, res
+
+
+def bench_composite128(args, dpr, torch, dev):
+    """K = 128 sort-last composite at 3840x2160 (one GPU's share of a 128-rank frame)."""
+    from synth import synthetic_frames
+    K, W, H = 128, 3840, 2160
+    rgba = torch.empty((K, H, W, 4), dtype=torch.float32, device=dev.torch_device)
+    depth = torch.empty((K, H, W), dtype=torch.float32, device=dev.torch_device)
+    synthetic_frames(K, W, H, 2.2, 3.4, 6005, dev.torch_device, rgba, depth)
+    frames = [dpr.Frame(dev, W, H, rgba=rgba[k], depth=depth[k]) for k in range(K)]
+    out = dpr.Frame(dev, W, H)
+    ids = list(np.random.default_rng(6005).permutation(K))
+    for _ in range(2):
+        dpr.composite(dev, frames, out, ids=ids)
+    torch.cuda.synchronize()
+    n = max(3, args.steps)
+    evs = [_events(torch) for _ in range(n)]
+    for e in evs:
+        e[0].record()
+        dpr.composite(dev, frames, out, ids=ids)
+        e[1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    live = int(torch.isfinite(depth).sum().item())
+    alg = K * W * H * 4 + live * 16 + W * H * 20
+    dense = K * W * H * 20 + W * H * 20
+    for f in frames + [out]:
+        f.release()
+    del rgba, depth
+    torch.cuda.empty_cache()
+    gbs = alg / ms / 1e6
+    return dict(workload="K=128 sort-last composite, 3840x2160, synthetic RGBA32F+depth frames",
+                ms=ms, algorithmic_bytes=alg, dense_bytes=dense, GBps=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sections", default="composite128")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    cfg = get_config("cfg2")
+    dims = cfg.dims
+    log("generating the 512^3 volume and its 8 bricks")
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+    tf = make_tf(cfg.seeds["tf"])
+    cam = orbit_camera(dims, *cfg.image)
+    boxes = even_split(dims, cfg.parts)
+    bricks = [extract_brick(vol, dims, lo, hi, 1) for lo, hi in boxes]
+    del vol
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cores = min(16, len(os.sched_getaffinity(0)))
+        log(f"CPU oracle baseline on {cores} cores")
+        cpu = cpu_baseline(bricks, dims, tf, oracle.RenderParams(cfg.step_voxels, cfg.ert, cfg.density), cam,
+                           args.cpu_stride, cores)
+        log(f"CPU oracle: {cpu['value']:.2f} Msamples/s")
+
+    import torch
+    import paper_2407_00179_amd as dpr
+    log("GPU: default workload")
+    dev, r = bench_main(args, dpr, torch, bricks, dims, tf, cfg, cam)
+    msamples = r["samples"] / (r["ms_per_step"] / 1e3) / 1e6
+    achieved = OPS_PER_SAMPLE * r["samples"] / (r["march_ms_per_launch"] * len(bricks) / 1e3) / 1e12
+    line = {
+        "metric": "Msamples/s (logical ray-march samples, render + composite)",
+        "value": msamples,
+        "unit": "Msamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, "
+                               "step 0.5 voxel, ERT 0.99, 16^3 macrocells; commit + majorants + 8 partial "
+                               "renders + K=8 composite per step",
+                   "logical_samples_per_step": r["samples"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "march_kernel", "ms_per_launch": r["march_ms_per_launch"],
+                     "ops_per_sample": OPS_PER_SAMPLE},
+        "composite_k8": {"ms": r["comp_ms"], "algorithmic_bytes": r["comp_bytes"],
+                         "GBps": r["comp_bytes"] / r["comp_ms"] / 1e6,
+                         "frac_hbm": r["comp_bytes"] / r["comp_ms"] / 1e6 / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+    }
+    secs = [s for s in args.sections.split(",") if s]
+    if "composite128" in secs:
+        log("GPU: K=128 composite at 3840x2160")
+        line["composite_k128"] = bench_composite128(args, dpr, torch, dev)
+    dev.release()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,8 +180,9 @@ struct BatchState {
   // key
   std::vector<dpr_camera> cams;
   std::vector<dpr_frame> outs;
+  std::vector<const void*> out_ptrs;
   int tile_w = 0, tile_h = 0;
-  uint64_t tf_version = 0;
+  uint64_t version = 0;
   bool skip = true;
   // device data
   CamG* d_cams = nullptr;
@@ -320,9 +321,14 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   b->free_device();
   b->cams.assign(cams, cams + n);
   b->outs.assign(outs, outs + n);
+  b->out_ptrs.clear();
+  for (int c = 0; c < n; ++c) {
+    b->out_ptrs.push_back(outs[c]->rgba);
+    b->out_ptrs.push_back(outs[c]->depth);
+  }
   b->tile_w = tw;
   b->tile_h = th;
-  b->tf_version = w->tf_version;
+  b->version = w->version;
   b->skip = !(w->params.flags & DPR_FLAG_NO_SKIP);
   const SceneG sc = make_scene(w);
   std::vector<CamG> cg(n);
@@ -428,10 +434,11 @@ static dpr_status capture_graph(dpr_world w, BatchState* b) {
 static bool same_key(const BatchState* b, dpr_world w, const dpr_camera* cams, int n, const dpr_frame* outs, int tw,
                      int th) {
   if (!b || b->tile_w != tw || b->tile_h != th || (int)b->cams.size() != n) return false;
-  if (b->skip != !(w->params.flags & DPR_FLAG_NO_SKIP)) return false;
+  if (b->version != w->version) return false;
   if (memcmp(b->cams.data(), cams, n * sizeof(dpr_camera)) != 0) return false;
   for (int c = 0; c < n; ++c)
-    if (b->outs[c] != outs[c]) return false;
+    if (b->outs[c] != outs[c] || b->out_ptrs[2 * c] != outs[c]->rgba || b->out_ptrs[2 * c + 1] != outs[c]->depth)
+      return false;
   return b->d_items != nullptr;
 }
 
@@ -506,12 +513,7 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
     DPR_HIP(enqueue_batch(w, b, w->dev->stream));
     return DPR_OK;
   }
-  if (!b->exec || b->tf_version != w->tf_version) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    b->tf_version = w->tf_version;
+  if (!b->exec) {
     s = capture_graph(w, b);
     if (s != DPR_OK) return s;
   }

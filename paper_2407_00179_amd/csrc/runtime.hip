@@ -474,6 +474,7 @@ dpr_status dpr_world_commit(dpr_world w) {
   }
   DPR_HIP(hipStreamSynchronize(w->dev->stream));
   w->committed = true;
+  ++w->version;
   return DPR_OK;
 }
 
@@ -530,6 +531,7 @@ dpr_status dpr_set_transfer_function(dpr_world w, const float* rgba, int32_t n, 
   w->density = density;
   w->tf_set = true;
   ++w->tf_version;
+  ++w->version;
   return DPR_OK;
 }
 
@@ -554,6 +556,7 @@ dpr_status dpr_set_render_params(dpr_world w, const dpr_render_params* p) {
                 mc);
   if (mc != w->params.macrocell_cells) w->committed = false;
   w->params = *p;
+  ++w->version;
   return DPR_OK;
 }
 

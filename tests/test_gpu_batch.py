@@ -1,0 +1,133 @@
+"""GPU tests of the persistent batched renderer (work queue + HIP graph + autotuned tiles)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import RenderParams
+from synth import Camera, fibonacci_cameras, kd_split, make_blobs, make_tf, make_volume_small
+from tests.gpu_util import TOL_F32, frame_np, log, make_world, oracle_brick
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dpr():
+    import paper_2407_00179_amd as m
+    return m
+
+
+def _scene(dtype=np.float32, dims=(56, 48, 40), nb=7, seed=61):
+    vol = make_volume_small(dims, make_blobs(dims, seed, 6, (0.06, 0.2)), seed + 1, 0.02, dtype)
+    boxes = kd_split(dims, nb, seed=seed, max_ratio=4.0)
+    return dims, vol, boxes, make_tf(2001)
+
+
+def _cams(dims):
+    cams = fibonacci_cameras(dims, 3, 96, 80)
+    cams[1] = Camera(cams[1].eye, cams[1].center, cams[1].up, 50.0, 131, 67)   # ragged size
+    cams.append(Camera((0.45, 0.4, 0.35), (1.5, 1.2, 0.9), (0.0, 0.0, 1.0), 80.0, 70, 70))  # eye inside
+    return cams
+
+
+def _reference(dpr, dev, w, cams):
+    outs = []
+    for c in cams:
+        w.set_camera(c)
+        f = dpr.Frame(dev, c.width, c.height)
+        w.render_frame(f)
+        outs.append(frame_np(f)[:2])
+        f.release()
+    return outs
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("ert", [0.99, 1.0])
+def test_batch_equals_render_frame_bitwise(gpu_lib, dpr, dtype, ert):
+    dims, vol, boxes, tf = _scene(dtype)
+    prm = RenderParams(0.5, ert, 25.0)
+    cams = _cams(dims)
+    log(f"batch {dtype.__name__} ert {ert}: {len(boxes)} bricks, {len(cams)} cameras")
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    ref = _reference(dpr, gpu_lib, w, cams)
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    for flags, what in ((0, "graph"), (dpr.FLAG_NO_GRAPH, "direct"), (dpr.FLAG_PLAIN, "plain")):
+        for f in frames:
+            f.rgba.fill_(-1.0)
+            f.depth.fill_(-1.0)
+        w.render_batch(cams, frames, flags)
+        for c, f in enumerate(frames):
+            got = frame_np(f)[:2]
+            assert np.array_equal(got[0], ref[c][0]), (what, c, np.max(np.abs(got[0] - ref[c][0])))
+            assert np.array_equal(got[1], ref[c][1]), (what, c)
+    w.release()
+
+
+def test_graph_replays_stay_exact(gpu_lib, dpr):
+    import torch
+    dims, vol, boxes, tf = _scene()
+    prm = RenderParams(0.5, 0.99, 25.0)
+    cams = _cams(dims)
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    ref = _reference(dpr, gpu_lib, w, cams)
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    for rep in range(5):
+        for f in frames:
+            f.rgba.fill_(float(rep))          # eager work between replays
+        junk = torch.randn(1 << 20, device=gpu_lib.torch_device).sum().item()
+        assert np.isfinite(junk)
+        w.render_batch(cams, frames)
+        for c, f in enumerate(frames):
+            got = frame_np(f)[:2]
+            assert np.array_equal(got[0], ref[c][0]) and np.array_equal(got[1], ref[c][1]), (rep, c)
+    # a new transfer function invalidates the captured graph
+    tf2 = make_tf(77)
+    w.set_transfer_function(tf2, 0.0, 1.0, 25.0)
+    ref2 = _reference(dpr, gpu_lib, w, cams)
+    w.render_batch(cams, frames)
+    for c, f in enumerate(frames):
+        assert np.array_equal(frame_np(f)[0], ref2[c][0])
+    w.release()
+
+
+def test_autotune_and_tile_shapes(gpu_lib, dpr):
+    dims, vol, boxes, tf = _scene(np.float16)
+    prm = RenderParams(0.5, 0.99, 25.0)
+    cams = _cams(dims)
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    ref = _reference(dpr, gpu_lib, w, cams)
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    tw, th = w.autotune_batch(cams, frames)
+    log(f"autotuned tile {tw}x{th}")
+    assert (tw * th) % 64 == 0
+    for shape in ((8, 8), (32, 16), (64, 1), (tw, th)):
+        w.set_batch_tile(*shape)
+        w.render_batch(cams, frames)
+        for c, f in enumerate(frames):
+            assert np.array_equal(frame_np(f)[0], ref[c][0]), (shape, c)
+    with pytest.raises(dpr.DprError):
+        w.set_batch_tile(7, 7)
+    with pytest.raises(dpr.DprError):
+        w.set_batch_tile(64, 32)
+    w.release()
+
+
+def test_batch_against_oracle(gpu_lib, dpr):
+    dims, vol, boxes, tf = _scene()
+    prm = RenderParams(0.5, 1.0, 25.0)
+    cams = _cams(dims)[:2]
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    w.render_batch(cams, frames)
+    for c, f in zip(cams, frames):
+        py, px = np.mgrid[0:c.height, 0:c.width]
+        px, py = px.ravel(), py.ravel()
+        orc = [oracle_brick(vol, dims, lo, hi, tf, prm, c, px, py) for lo, hi in boxes]
+        want, wz = oracle.composite(np.stack([o[0] for o in orc]), np.stack([o[1] for o in orc]))
+        got, gz, _ = frame_np(f)
+        err = np.max(np.abs(got - want))
+        log(f"  batch vs oracle {c.width}x{c.height}: {err:.3e}")
+        assert err <= TOL_F32
+        fin = np.isfinite(wz)
+        assert np.array_equal(np.isfinite(gz), fin)
+    w.release()
