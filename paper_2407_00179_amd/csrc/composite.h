@@ -35,8 +35,15 @@ __device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool liv
     s.rank[k] = rank_of(k);
     s.order[k] = (unsigned char)k;  // every slot holds a valid source even if ranks collided
   }
-  // 1. depths of the tile, coalesced per source
-  for (int k = 0; k < K; ++k) s.zs[k][lane] = live_px ? depth_of(k) : INFINITY;
+  // 1. depths of the tile, coalesced per source, 16 loads in flight per lane
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = (live_px && k0 + u < K) ? depth_of(k0 + u) : INFINITY;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (k0 + u < K) s.zs[k0 + u][lane] = v[u];
+  }
   __syncthreads();
   // 2. tile order of the sources by (nearest depth in the tile, id rank)
   for (int k = lane; k < K; k += 64) {
@@ -85,12 +92,12 @@ __device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool liv
   // 4. front-to-back over, RGBA fetched for live fragments only
   float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f;
   int i = 0;
-  for (; i + 4 <= n; i += 4) {
-    float4 f[4];
+  for (; i + 8 <= n; i += 8) {
+    float4 f[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) f[u] = rgba_of(s.lst[i + u][lane]);
+    for (int u = 0; u < 8; ++u) f[u] = rgba_of(s.lst[i + u][lane]);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       cr = fmaf(tr, f[u].x, cr);
       cg = fmaf(tr, f[u].y, cg);
       cb = fmaf(tr, f[u].z, cb);

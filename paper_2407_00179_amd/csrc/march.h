@@ -1,21 +1,29 @@
 // Resumable per-ray emission-absorption march through one brick.
 //
-// The plain per-brick kernel runs a ray to completion in one call; the
-// persistent batched kernel advances rays a few segments at a time so a wave can
-// refill lanes whose rays have finished.  Both use exactly this code, so both
-// produce the same bits for the same ray.
+// Sample points advance in exact 32.32 fixed point (global voxel-centre units),
+// so the point of segment s is the same integer whichever way the ray got there:
+// in one call, in budgeted slices (persistent kernel), with or without skipping.
+// The lattice is walked in runs of consecutive segments whose sample points share
+// one macrocell; the run length is computed exactly in integers, a run in a
+// macrocell of majorant 0 is skipped in O(1), and the other runs sample every
+// segment with no per-sample macrocell logic.  Voxel gathers of the next sample
+// are issued before the current sample is shaded.
 #pragma once
 
 #include "device_common.h"
 
 namespace dpr {
 
+constexpr double kFix = 4294967296.0;  // 2^32
+
 struct RayState {
-  double ov[3], dv[3];   // origin and direction in global voxel-centre units
+  int64_t p[3];          // sample point of segment s, 32.32 fixed point (global voxel-centre coords)
+  int64_t dp[3];         // advance per segment
   double t_in, t_out;    // clipped parametric range (world units)
   double tau;            // optical depth accumulated so far
-  int s, s1;             // next lattice segment, last lattice segment
+  int s, s0, s1;         // next segment, first and last segment
   int n;                 // logical samples processed
+  float dl_first, dl_last;  // D * clipped length of the first / last segment
   float T, cr, cg, cb;   // transmittance and premultiplied colour
 };
 
@@ -30,12 +38,32 @@ __device__ __forceinline__ bool ray_begin(const SceneG& sc, const BrickG& b, con
     hi[a] = b.ohi[a] * sc.h;
   }
   if (!clip_box(o, d, lo, hi, r.t_in, r.t_out)) return false;
-  r.s = (int)floor(r.t_in / sc.dt);
-  r.s1 = (int)ceil(r.t_out / sc.dt) - 1;
+  const double dt = sc.dt;
+  int s0 = (int)floor(r.t_in / dt);
+  int s1 = (int)ceil(r.t_out / dt) - 1;
+  // lengths of the clipped end segments; a non-positive one is dropped
+  double lf = fmin((s0 + 1) * dt, r.t_out) - fmax(s0 * dt, r.t_in);
+  if (!(lf > 0.0)) {
+    ++s0;
+    lf = fmin((s0 + 1) * dt, r.t_out) - fmax(s0 * dt, r.t_in);
+  }
+  double ll = fmin((s1 + 1) * dt, r.t_out) - fmax(s1 * dt, r.t_in);
+  if (!(ll > 0.0)) {
+    --s1;
+    ll = fmin((s1 + 1) * dt, r.t_out) - fmax(s1 * dt, r.t_in);
+  }
+  // (s1 < s0 only through rounding at a vanishing chord: a hit with no samples)
+  r.s = r.s0 = s0;
+  r.s1 = s1;
+  r.dl_first = sc.density * (float)lf;
+  r.dl_last = sc.density * (float)ll;
+  const double tm = (s0 + 0.5) * dt;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    r.ov[a] = o[a] * sc.inv_h - 0.5;
-    r.dv[a] = d[a] * sc.inv_h;
+    const double dv = d[a] * sc.inv_h;
+    const double g = fma(tm, dv, o[a] * sc.inv_h - 0.5);
+    r.p[a] = __double2ll_rn(g * kFix);
+    r.dp[a] = __double2ll_rn(dt * dv * kFix);
   }
   r.tau = 0.0;
   r.n = 0;
@@ -44,98 +72,178 @@ __device__ __forceinline__ bool ray_begin(const SceneG& sc, const BrickG& b, con
   return true;
 }
 
+// Largest j >= 0 with p + j*dp inside [b_lo, b_hi) on one axis (the current point
+// is inside).  Exact: floating-point quotient corrected in integers.
+__device__ __forceinline__ int steps_inside(int64_t p, int64_t dp, int64_t b_lo, int64_t b_hi, int cap) {
+  int64_t num, den;
+  if (dp > 0) {
+    if (b_hi == INT64_MAX) return cap;
+    num = b_hi - 1 - p;
+    den = dp;
+  } else if (dp < 0) {
+    if (b_lo == INT64_MIN) return cap;
+    num = p - b_lo;
+    den = -dp;
+  } else {
+    return cap;
+  }
+  int64_t q = (int64_t)((double)num / (double)den);
+  if (q * den > num) --q;
+  else if ((q + 1) * den <= num) ++q;
+  return q < (int64_t)cap ? (int)q : cap;
+}
+
+__device__ __forceinline__ void clamp_axis(int64_t p, int n, int slo, int sdim, int& l, float& f) {
+  const int hi = (int)(p >> 32);
+  float fr = (float)(uint32_t)(p & 0xffffffffll) * (1.0f / 4294967296.0f);
+  fr = (hi < 0) ? 0.f : ((hi > n - 2) ? 1.f : fr);
+  const int i0 = min(max(hi, 0), n - 2);
+  // commit guarantees i0 - slo lies in [0, sdim - 2]; the clamp only guards memory
+  l = min(max(i0 - slo, 0), sdim - 2);
+  f = fr;
+}
+
+template <typename T>
+struct Gather {
+  float v[8];
+  float fx, fy, fz;
+};
+
+template <typename T>
+__device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const T* vox, const int64_t p[3],
+                                       Gather<T>& g) {
+  int lx, ly, lz;
+  clamp_axis(p[0], sc.dims[0], b.slo[0], b.sdim[0], lx, g.fx);
+  clamp_axis(p[1], sc.dims[1], b.slo[1], b.sdim[1], ly, g.fy);
+  clamp_axis(p[2], sc.dims[2], b.slo[2], b.sdim[2], lz, g.fz);
+  const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
+  const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
+  const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
+  g.v[0] = load_voxel<T>(vox, x0 + y0 + z0);
+  g.v[1] = load_voxel<T>(vox, x1 + y0 + z0);
+  g.v[2] = load_voxel<T>(vox, x0 + y1 + z0);
+  g.v[3] = load_voxel<T>(vox, x1 + y1 + z0);
+  g.v[4] = load_voxel<T>(vox, x0 + y0 + z1);
+  g.v[5] = load_voxel<T>(vox, x1 + y0 + z1);
+  g.v[6] = load_voxel<T>(vox, x0 + y1 + z1);
+  g.v[7] = load_voxel<T>(vox, x1 + y1 + z1);
+}
+
+// Shade one sample; returns true when the ray terminates early.
+template <typename T>
+__device__ __forceinline__ bool shade(const SceneG& sc, const float4* __restrict__ tfb,
+                                      const float4* __restrict__ tfs, const Gather<T>& g, float Dl, double& tau_acc,
+                                      float& tr, float& cr, float& cg, float& cb) {
+  const float c00 = fmaf(g.fx, g.v[1] - g.v[0], g.v[0]), c01 = fmaf(g.fx, g.v[3] - g.v[2], g.v[2]);
+  const float c10 = fmaf(g.fx, g.v[5] - g.v[4], g.v[4]), c11 = fmaf(g.fx, g.v[7] - g.v[6], g.v[6]);
+  const float c0 = fmaf(g.fy, c01 - c00, c00), c1 = fmaf(g.fy, c11 - c10, c10);
+  const float v = fmaf(g.fz, c1 - c0, c0);
+  float x = (v - sc.tf_lo) * sc.tf_scale;
+  x = fminf(fmaxf(x, 0.f), (float)(sc.ntf - 1));
+  const int j = min((int)x, sc.ntf - 2);
+  const float w = x - (float)j;
+  const float4 tb = tfb[j], ts = tfs[j];
+  const float A = fmaf(w, ts.w, tb.w);
+  const float tau = Dl * A;
+  if (tau > 0.f) {
+    tau_acc += (double)tau;
+    const float tn = __expf(-(float)tau_acc);
+    const float wgt = tr - tn;
+    cr = fmaf(wgt, fmaf(w, ts.x, tb.x), cr);
+    cg = fmaf(wgt, fmaf(w, ts.y, tb.y), cg);
+    cb = fmaf(wgt, fmaf(w, ts.z, tb.z), cb);
+    tr = tn;
+    return 1.f - tr >= sc.ert;
+  }
+  return false;
+}
+
 // Advance by at most `budget` lattice segments.  Returns true once the ray is
 // finished: past its last segment, or terminated early (1 - T >= ert, tested
 // after every segment that changed T).
 template <typename T, bool SKIP>
 __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
                                             const float4* __restrict__ tfs, RayState& r, int budget) {
-  const double dt = sc.dt;
   const T* vox = (const T*)b.data;
-  const double nx1 = sc.dims[0] - 1, ny1 = sc.dims[1] - 1, nz1 = sc.dims[2] - 1;
   const float Ddt = sc.density * sc.dt_f;
   int s = r.s;
-  const int s1 = r.s1;
-  const int s_end = (s1 - s < budget) ? s1 : s + budget - 1;
+  int n = r.n;
+  int64_t p0 = r.p[0], p1 = r.p[1], p2 = r.p[2];
+  const int64_t d0 = r.dp[0], d1 = r.dp[1], d2 = r.dp[2];
   float tr = r.T, cr = r.cr, cg = r.cg, cb = r.cb;
   double tau_acc = r.tau;
-  int n = r.n;
   bool done = false;
-  for (; s <= s_end; ++s) {
-    const double tlo = (double)s * dt;
-    const double thi = tlo + dt;
-    float Dl = Ddt;
-    if (tlo < r.t_in || thi > r.t_out) {
-      double l = fmin(thi, r.t_out) - fmax(tlo, r.t_in);
-      if (!(l > 0.0)) continue;
-      Dl = sc.density * (float)l;
-    }
-    ++n;
-    const double tm = tlo + 0.5 * dt;
-    const double gx = fma(tm, r.dv[0], r.ov[0]);
-    const double gy = fma(tm, r.dv[1], r.ov[1]);
-    const double gz = fma(tm, r.dv[2], r.ov[2]);
+  while (!done && s <= r.s1 && budget > 0) {
+    int run = min(r.s1 - s + 1, budget);
+    bool empty = false;
     if (SKIP) {
-      int mx = ((int)floor(gx + 0.5) - b.olo[0]) >> b.mc_shift;
-      int my = ((int)floor(gy + 0.5) - b.olo[1]) >> b.mc_shift;
-      int mz = ((int)floor(gz + 0.5) - b.olo[2]) >> b.mc_shift;
-      mx = min(max(mx, 0), b.mdim[0] - 1);
-      my = min(max(my, 0), b.mdim[1] - 1);
-      mz = min(max(mz, 0), b.mdim[2] - 1);
-      if (b.majorant[(mz * b.mdim[1] + my) * b.mdim[0] + mx] == 0.f) continue;
+      // macrocell of the current sample point: cell = floor(g + 1/2)
+      const int64_t half = 0x80000000ll;
+      int m[3];
+      const int64_t pp[3] = {p0, p1, p2};
+      const int64_t dd[3] = {d0, d1, d2};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int cell = (int)((pp[a] + half) >> 32);
+        int ma = (cell - b.olo[a]) >> b.mc_shift;
+        ma = min(max(ma, 0), b.mdim[a] - 1);
+        m[a] = ma;
+        // fixed-point bounds of this macrocell's sample points (outer cells unbounded)
+        const int64_t blo = (ma == 0) ? INT64_MIN
+                                      : ((int64_t)(b.olo[a] + (ma << b.mc_shift)) << 32) - half;
+        const int64_t bhi = (ma == b.mdim[a] - 1) ? INT64_MAX
+                                                  : ((int64_t)(b.olo[a] + ((ma + 1) << b.mc_shift)) << 32) - half;
+        run = min(run, 1 + steps_inside(pp[a], dd[a], blo, bhi, run - 1));
+      }
+      empty = b.majorant[(m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]] == 0.f;
     }
-    const double cx = fmin(fmax(gx, 0.0), nx1);
-    const double cy = fmin(fmax(gy, 0.0), ny1);
-    const double cz = fmin(fmax(gz, 0.0), nz1);
-    const int ix = min((int)floor(cx), sc.dims[0] - 2);
-    const int iy = min((int)floor(cy), sc.dims[1] - 2);
-    const int iz = min((int)floor(cz), sc.dims[2] - 2);
-    const float fx = (float)(cx - ix), fy = (float)(cy - iy), fz = (float)(cz - iz);
-    // commit guarantees these lie in [0, sdim - 2]; the clamp only guards memory
-    const int lx = min(max(ix - b.slo[0], 0), b.sdim[0] - 2);
-    const int ly = min(max(iy - b.slo[1], 0), b.sdim[1] - 2);
-    const int lz = min(max(iz - b.slo[2], 0), b.sdim[2] - 2);
-    const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
-    const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
-    const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
-    const float v000 = load_voxel<T>(vox, x0 + y0 + z0), v001 = load_voxel<T>(vox, x1 + y0 + z0);
-    const float v010 = load_voxel<T>(vox, x0 + y1 + z0), v011 = load_voxel<T>(vox, x1 + y1 + z0);
-    const float v100 = load_voxel<T>(vox, x0 + y0 + z1), v101 = load_voxel<T>(vox, x1 + y0 + z1);
-    const float v110 = load_voxel<T>(vox, x0 + y1 + z1), v111 = load_voxel<T>(vox, x1 + y1 + z1);
-    const float c00 = fmaf(fx, v001 - v000, v000), c01 = fmaf(fx, v011 - v010, v010);
-    const float c10 = fmaf(fx, v101 - v100, v100), c11 = fmaf(fx, v111 - v110, v110);
-    const float c0 = fmaf(fy, c01 - c00, c00), c1 = fmaf(fy, c11 - c10, c10);
-    const float v = fmaf(fz, c1 - c0, c0);
-    float x = (v - sc.tf_lo) * sc.tf_scale;
-    x = fminf(fmaxf(x, 0.f), (float)(sc.ntf - 1));
-    const int j = min((int)x, sc.ntf - 2);
-    const float w = x - (float)j;
-    const float4 tb = tfb[j], ts = tfs[j];
-    const float A = fmaf(w, ts.w, tb.w);
-    const float tau = Dl * A;
-    if (tau > 0.f) {
-      tau_acc += (double)tau;
-      const float tn = __expf(-(float)tau_acc);
-      const float wgt = tr - tn;
-      cr = fmaf(wgt, fmaf(w, ts.x, tb.x), cr);
-      cg = fmaf(wgt, fmaf(w, ts.y, tb.y), cg);
-      cb = fmaf(wgt, fmaf(w, ts.z, tb.z), cb);
-      tr = tn;
-      if (1.f - tr >= sc.ert) {
+    if (empty) {  // every sample in the run has opacity exactly 0
+      s += run;
+      n += run;
+      budget -= run;
+      p0 += (int64_t)run * d0;
+      p1 += (int64_t)run * d1;
+      p2 += (int64_t)run * d2;
+      continue;
+    }
+    budget -= run;
+    Gather<T> cur;
+    {
+      const int64_t pc[3] = {p0, p1, p2};
+      gather<T>(sc, b, vox, pc, cur);
+    }
+    for (int i = 0; i < run; ++i) {
+      p0 += d0;
+      p1 += d1;
+      p2 += d2;
+      Gather<T> nxt;
+      const bool more = i + 1 < run;
+      if (more) {
+        const int64_t pn[3] = {p0, p1, p2};
+        gather<T>(sc, b, vox, pn, nxt);
+      }
+      const float Dl = (s == r.s0) ? r.dl_first : ((s == r.s1) ? r.dl_last : Ddt);
+      ++n;
+      ++s;
+      if (shade<T>(sc, tfb, tfs, cur, Dl, tau_acc, tr, cr, cg, cb)) {
         done = true;
-        ++s;
         break;
       }
+      if (more) cur = nxt;
     }
   }
+  // the fixed-point position always corresponds to segment s
   r.s = s;
+  r.p[0] = p0;
+  r.p[1] = p1;
+  r.p[2] = p2;
   r.T = tr;
   r.cr = cr;
   r.cg = cg;
   r.cb = cb;
   r.tau = tau_acc;
   r.n = n;
-  return done || s > s1;
+  return done || s > r.s1;
 }
 
 // Stage the TF as (entry, next - entry) pairs so a lookup is one FMA per channel.
