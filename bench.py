@@ -94,51 +94,46 @@ def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
     w.set_camera(cam)
     W, H = cfg.image
     K = len(vol_bricks)
-    parts = [dpr.Frame(dev, W, H) for _ in range(K)]
     out = dpr.Frame(dev, W, H)
-    # logical samples of one frame (counts attached for one untimed pass)
-    total = 0
-    for i, f in enumerate(parts):
-        c = f.attach_counts()
-        w.render_partial(i, f)
-        dev.sync()
-        total += int(c.sum().item())
-        dpr.check(dpr.lib.dpr_frame_attach_counts(f.h, None))
-        f.counts = None
+    total = _count_samples(dpr, dev, w, [cam], K)
+    w.set_camera(cam)
 
-    def step(ev=None):
-        w.commit()
-        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
-        for i, f in enumerate(parts):
-            if ev is not None:
-                ev["march"][i][0].record()
-            w.render_partial(i, f)
-            if ev is not None:
-                ev["march"][i][1].record()
-        if ev is not None:
-            ev["comp"][0].record()
-        dpr.composite(dev, parts, out, ids=list(range(K)))
-        if ev is not None:
-            ev["comp"][1].record()
+    def step():
+        w.commit()                                        # relayout + macrocell ranges
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)  # majorants follow
+        w.render_frame(out)                               # batched march + tile composite
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [dict(march=[_events(torch) for _ in range(K)], comp=_events(torch)) for _ in range(args.steps)]
+    march_ms, comp_ms = [], []
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(evs[s])
+    for _ in range(args.steps):
+        step()
+        a, c = w.batch_timings()          # HIP events recorded around each kernel on the device stream
+        march_ms.append(a)
+        comp_ms.append(c)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    march_ms = [e["march"][i][0].elapsed_time(e["march"][i][1]) for e in evs for i in range(K)]
-    comp_ms = [e["comp"][0].elapsed_time(e["comp"][1]) for e in evs]
     ms_step = wall * 1e3 / args.steps
-    # compositor algorithmic bytes: all depths, RGBA of live fragments, output
+    # the plain per-brick path on the same frame: 8 render_partial launches + dpr_composite
+    parts = [dpr.Frame(dev, W, H) for _ in range(K)]
+
+    def plain():
+        for i, f in enumerate(parts):
+            w.render_partial(i, f)
+        dpr.composite(dev, parts, out, ids=list(range(K)))
+
+    plain()
+    torch.cuda.synchronize()
+    ms_plain = _timed(torch, plain, max(3, args.steps))
+    ms_plain_march = _timed(torch, lambda: [w.render_partial(i, f) for i, f in enumerate(parts)], max(3, args.steps))
     live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
     comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
-    res = dict(ms_per_step=ms_step, samples=total, march_ms_per_launch=float(np.mean(march_ms)),
-               march_ms_per_frame=float(np.mean(march_ms)) * K, comp_ms=float(np.mean(comp_ms)),
-               comp_bytes=comp_bytes, live_fragments=live)
+    ms_comp8 = _timed(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), max(3, args.steps))
+    res = dict(ms_per_step=ms_step, samples=total, march_ms=float(np.mean(march_ms)),
+               tile_comp_ms=float(np.mean(comp_ms)), ms_plain=ms_plain, ms_plain_march=ms_plain_march,
+               comp8_ms=ms_comp8, comp_bytes=comp_bytes)
     w.release()
     for f in parts + [out]:
         f.release()
@@ -178,6 +173,75 @@ def bench_composite128(args, dpr, torch, dev):
                 ms=ms, algorithmic_bytes=alg, dense_bytes=dense, GBps=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
 
 
+def _timed(torch, fn, n):
+    evs = [_events(torch) for _ in range(n)]
+    for e in evs:
+        e[0].record()
+        fn()
+        e[1].record()
+    torch.cuda.synchronize()
+    return float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+
+
+def _count_samples(dpr, dev, w, cams, n_bricks):
+    total = 0
+    for c in cams:
+        w.set_camera(c)
+        f = dpr.Frame(dev, c.width, c.height, counts=True)
+        for i in range(n_bricks):
+            f.counts.zero_()
+            w.render_partial(i, f)
+            dev.sync()
+            total += int(f.counts.sum().item())
+        f.release()
+    return total
+
+
+def bench_batch(args, dpr, torch, dev, w, cams, n_bricks, reps):
+    """Persistent batched renderer (graph) vs plain per-brick launches, same world and cameras."""
+    frames = [dpr.Frame(dev, c.width, c.height) for c in cams]
+    samples = _count_samples(dpr, dev, w, cams, n_bricks)
+    tw, th = w.autotune_batch(cams, frames)
+    w.render_batch(cams, frames)
+    torch.cuda.synchronize()
+    ms_batch = _timed(torch, lambda: w.render_batch(cams, frames), reps)
+    w.render_batch(cams, frames, dpr.FLAG_PLAIN)
+    torch.cuda.synchronize()
+    ms_plain = _timed(torch, lambda: w.render_batch(cams, frames, dpr.FLAG_PLAIN), reps)
+    for f in frames:
+        f.release()
+    return dict(samples=samples, tile=[tw, th], ms_batch=ms_batch, ms_plain=ms_plain,
+                msamples_batch=samples / ms_batch / 1e3, msamples_plain=samples / ms_plain / 1e3,
+                speedup=ms_plain / ms_batch)
+
+
+def bench_cfg3(args, dpr, torch, dev):
+    """27 uneven k-d bricks of a 1024x1024x768 FP16 volume, 16 cameras at 2048x2048."""
+    from synth import fibonacci_cameras, kd_split, make_volume_large, brick_ghosts
+    cfg = get_config("cfg3")
+    dims = cfg.dims
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    vol = make_volume_large(dims, blobs, cfg.seeds["volume"], cfg.noise_amp, cfg.fbm_periods, device=dev.torch_device)
+    boxes = kd_split(dims, cfg.n_bricks, cfg.seeds["kd"], 4.0)
+    w = dpr.World(dev, dims)
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
+    for lo, hi in boxes:
+        glo, ghi = brick_ghosts(dims, lo, hi)
+        sl = vol[lo[2] - glo[2]:hi[2] + ghi[2], lo[1] - glo[1]:hi[1] + ghi[1], lo[0] - glo[0]:hi[0] + ghi[0]]
+        w.add_brick(sl.contiguous(), lo, hi, glo, ghi)
+    del vol
+    torch.cuda.empty_cache()
+    w.commit()
+    w.set_transfer_function(make_tf(cfg.seeds["tf"]), 0.0, 1.0, cfg.density)
+    cams = fibonacci_cameras(dims, cfg.n_cams, *cfg.image)
+    r = bench_batch(args, dpr, torch, dev, w, cams, len(boxes), 2)
+    w.release()
+    torch.cuda.empty_cache()
+    r["workload"] = ("1024x1024x768 FP16 blob+fBm volume, 27 k-d bricks (<=4:1), 16 cameras x 2048x2048, "
+                     "step 0.5 voxel, ERT 0.99")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,7 +249,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="composite128")
+    ap.add_argument("--sections", default="batch,cfg3,composite128")
+    ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -217,7 +282,7 @@ def main():
     log("GPU: default workload")
     dev, r = bench_main(args, dpr, torch, bricks, dims, tf, cfg, cam)
     msamples = r["samples"] / (r["ms_per_step"] / 1e3) / 1e6
-    achieved = OPS_PER_SAMPLE * r["samples"] / (r["march_ms_per_launch"] * len(bricks) / 1e3) / 1e12
+    achieved = OPS_PER_SAMPLE * r["samples"] / (r["march_ms"] / 1e3) / 1e12
     line = {
         "metric": "Msamples/s (logical ray-march samples, render + composite)",
         "value": msamples,
@@ -232,19 +297,36 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, "
-                               "step 0.5 voxel, ERT 0.99, 16^3 macrocells; commit + majorants + 8 partial "
-                               "renders + K=8 composite per step",
+                               "step 0.5 voxel, ERT 0.99, 16^3 macrocells; per step: commit (relayout + "
+                               "macrocell ranges), majorants, batched march of the 8 bricks, tile composite",
                    "logical_samples_per_step": r["samples"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "march_kernel", "ms_per_launch": r["march_ms_per_launch"],
+                     "kernel": "batch_march_kernel", "ms_per_launch": r["march_ms"],
                      "ops_per_sample": OPS_PER_SAMPLE},
-        "composite_k8": {"ms": r["comp_ms"], "algorithmic_bytes": r["comp_bytes"],
-                         "GBps": r["comp_bytes"] / r["comp_ms"] / 1e6,
-                         "frac_hbm": r["comp_bytes"] / r["comp_ms"] / 1e6 / HBM_PEAK_GBS},
+        "phases_ms": {"batch_march": r["march_ms"], "tile_composite": r["tile_comp_ms"]},
+        "plain_per_brick": {"ms_render_and_composite": r["ms_plain"], "ms_8_marches": r["ms_plain_march"],
+                            "msamples": r["samples"] / r["ms_plain"] / 1e3,
+                            "batched_speedup_march": r["ms_plain_march"] / r["march_ms"]},
+        "composite_k8": {"ms": r["comp8_ms"], "algorithmic_bytes": r["comp_bytes"],
+                         "GBps": r["comp_bytes"] / r["comp8_ms"] / 1e6,
+                         "frac_hbm": r["comp_bytes"] / r["comp8_ms"] / 1e6 / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
     }
-    secs = [s for s in args.sections.split(",") if s]
+    secs = [] if args.main_only else [s for s in args.sections.split(",") if s]
+    if "batch" in secs:
+        log("GPU: batched renderer on the default workload")
+        w = dpr.World(dev, dims)
+        w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
+        for b in bricks:
+            w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)
+        w.commit()
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+        line["batch_cfg2"] = bench_batch(args, dpr, torch, dev, w, [cam], len(bricks), max(3, args.steps))
+        w.release()
+    if "cfg3" in secs:
+        log("GPU: 27-brick 16-camera batched workload")
+        line["batch_cfg3"] = bench_cfg3(args, dpr, torch, dev)
     if "composite128" in secs:
         log("GPU: K=128 composite at 3840x2160")
         line["composite_k128"] = bench_composite128(args, dpr, torch, dev)

@@ -60,7 +60,7 @@ typedef enum { DPR_F32 = 0, DPR_F16 = 1 } dpr_dtype;
 
 /* render-parameter and call flags */
 #define DPR_FLAG_NO_SKIP 0x1u    /* disable macrocell empty-space skipping          */
-#define DPR_FLAG_PLAIN 0x2u      /* batch: one plain launch per (camera, brick)      */
+#define DPR_FLAG_PLAIN 0x2u      /* one plain launch per (camera, brick) + composite  */
 #define DPR_FLAG_NO_GRAPH 0x4u   /* batch: enqueue directly, no HIP graph replay     */
 
 typedef struct dpr_device_t* dpr_device; /* one GPU + one HIP stream              */
@@ -197,7 +197,11 @@ dpr_status dpr_composite(dpr_device, const dpr_frame* parts, const int32_t* frag
                          dpr_frame out);
 
 /* The collective render of section 3.2 on one GPU: render every brick of the
- * world into its own partial frame, then composite them into `out`.           */
+ * world to fragments and composite them into `out`.  By default the bricks go
+ * through the persistent batched renderer below (one camera); with
+ * DPR_FLAG_PLAIN in the render parameters each brick is rendered into its own
+ * partial frame by dpr_render_partial and the frames go through dpr_composite.
+ * Both give the same bits.                                                      */
 dpr_status dpr_render_frame(dpr_world, dpr_frame out);
 
 /* Batched render of n cameras: one persistent launch walks a queue of
@@ -210,8 +214,13 @@ dpr_status dpr_render_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_fr
  * keep the fastest for later dpr_render_batch calls; writes the chosen shape.  */
 dpr_status dpr_autotune_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_frame* outs,
                               int32_t* tile_w, int32_t* tile_h);
-/* Force a tile shape (tile_w * tile_h must be 64, a multiple of 64, <= 1024).  */
+/* Force a tile shape (tile_w * tile_h must be a multiple of 64, <= 1024).      */
 dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
+/* Durations of the march kernel and of the tile compositor of the last batched
+ * render (dpr_render_batch or dpr_render_frame), from HIP events recorded on the
+ * device stream around each kernel (also inside the replayed graph).
+ * Synchronises.  DPR_ERR_INVALID_STATE before any batched render.               */
+dpr_status dpr_batch_timings(dpr_world, float* march_ms, float* composite_ms);
 
 /* ---------------------------------------------------------------- training */
 /* Differentiable render of one whole volume (no bricks, ERT off) for n cameras.

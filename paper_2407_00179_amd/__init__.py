@@ -200,6 +200,12 @@ class World:
     def set_batch_tile(self, tw, th):
         check(lib.dpr_set_batch_tile(self.h, tw, th))
 
+    def batch_timings(self):
+        """(march_ms, composite_ms) of the last batched render, from HIP events."""
+        a, c = C.c_float(), C.c_float()
+        check(lib.dpr_batch_timings(self.h, C.byref(a), C.byref(c)))
+        return a.value, c.value
+
     def release(self):
         if self.h:
             lib.dpr_world_release(self.h)

@@ -35,13 +35,15 @@ __device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool liv
     s.rank[k] = rank_of(k);
     s.order[k] = (unsigned char)k;  // every slot holds a valid source even if ranks collided
   }
-  // 1. depths of the tile, coalesced per source, 16 loads in flight per lane
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    float v[16];
+  // 1. depths of the tile, coalesced per source.  Large K runs at a few waves per
+  //    CU (LDS-bound), so each lane keeps up to 64 loads in flight in registers.
+  constexpr int B = KMAX < 64 ? KMAX : 64;
+  for (int k0 = 0; k0 < K; k0 += B) {
+    float v[B];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = (live_px && k0 + u < K) ? depth_of(k0 + u) : INFINITY;
+    for (int u = 0; u < B; ++u) v[u] = (live_px && k0 + u < K) ? depth_of(k0 + u) : INFINITY;
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < B; ++u)
       if (k0 + u < K) s.zs[k0 + u][lane] = v[u];
   }
   __syncthreads();
@@ -91,13 +93,14 @@ __device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool liv
   }
   // 4. front-to-back over, RGBA fetched for live fragments only
   float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f;
+  constexpr int F = KMAX < 16 ? 8 : 16;  // RGBA loads in flight per lane
   int i = 0;
-  for (; i + 8 <= n; i += 8) {
-    float4 f[8];
+  for (; i + F <= n; i += F) {
+    float4 f[F];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) f[u] = rgba_of(s.lst[i + u][lane]);
+    for (int u = 0; u < F; ++u) f[u] = rgba_of(s.lst[i + u][lane]);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < F; ++u) {
       cr = fmaf(tr, f[u].x, cr);
       cg = fmaf(tr, f[u].y, cg);
       cb = fmaf(tr, f[u].z, cb);

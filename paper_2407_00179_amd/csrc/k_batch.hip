@@ -202,6 +202,8 @@ struct BatchState {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // before march, after march, after composite
+  bool timed = false;                               // events were recorded by the last render
   // plain per-brick path
   std::vector<dpr_frame> plain_parts;
 
@@ -228,6 +230,8 @@ struct BatchState {
     free_device();
     for (auto f : plain_parts) dpr_frame_release(f);
     if (cap) (void)hipStreamDestroy(cap);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -287,6 +291,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
   const bool f16 = w->bricks[0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, b->head);
+  if (b->ev[0]) (void)hipEventRecord(b->ev[0], st);
   if (f16) {
     if (b->skip)
       hipLaunchKernelGGL((batch_march_kernel<__half, true>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
@@ -298,6 +303,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
     else
       hipLaunchKernelGGL((batch_march_kernel<float, false>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
   }
+  if (b->ev[1]) (void)hipEventRecord(b->ev[1], st);
   const int tp = b->tile_w * b->tile_h;
   const int chunks = (tp + 63) / 64;
   dim3 cgrid((unsigned)b->n_tiles * chunks);
@@ -310,6 +316,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
   else
     hipLaunchKernelGGL(tile_composite_kernel<256>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
                        b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
+  if (b->ev[2]) (void)hipEventRecord(b->ev[2], st);
   return hipGetLastError();
 }
 
@@ -399,6 +406,8 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   if ((s = dev_alloc((void**)&b->frag_rgba, frags * sizeof(float4), "batch fragments")) != DPR_OK) return s;
   if ((s = dev_alloc((void**)&b->frag_depth, frags * sizeof(float), "batch fragment depths")) != DPR_OK) return s;
   if ((s = dev_alloc((void**)&b->head, sizeof(int), "batch queue head")) != DPR_OK) return s;
+  for (auto& e : b->ev)
+    if (!e) DPR_HIP(hipEventCreate(&e));
   // persistent grid: as many 256-thread workgroups as fit on the GPU at once
   int per_cu = 0;
   const bool f16 = w->bricks[0].dtype == DPR_F16;
@@ -511,6 +520,7 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
   }
   if (flags & DPR_FLAG_NO_GRAPH) {
     DPR_HIP(enqueue_batch(w, b, w->dev->stream));
+    b->timed = true;
     return DPR_OK;
   }
   if (!b->exec) {
@@ -518,7 +528,12 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
     if (s != DPR_OK) return s;
   }
   DPR_HIP(hipGraphLaunch(b->exec, w->dev->stream));
+  b->timed = true;
   return DPR_OK;
+}
+
+dpr_status render_frame_batched(dpr_world w, dpr_frame out) {
+  return render_batch_tiled(w, &w->cam, 1, &out, 0, w->batch_tile_w, w->batch_tile_h);
 }
 
 }  // namespace dpr
@@ -536,6 +551,19 @@ dpr_status dpr_render_batch(dpr_world w, const dpr_camera* cams, int32_t n, dpr_
     return render_plain(w, cams, n, outs);
   }
   return render_batch_tiled(w, cams, n, outs, flags, w->batch_tile_w, w->batch_tile_h);
+}
+
+dpr_status dpr_batch_timings(dpr_world w, float* march_ms, float* composite_ms) {
+  if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_batch_timings: NULL world");
+  BatchState* b = w->batch;
+  if (!b || !b->timed || !b->ev[0]) return fail(DPR_ERR_INVALID_STATE, "dpr_batch_timings: no batched render yet");
+  DPR_HIP(hipEventSynchronize(b->ev[2]));
+  float a = 0.f, c = 0.f;
+  DPR_HIP(hipEventElapsedTime(&a, b->ev[0], b->ev[1]));
+  DPR_HIP(hipEventElapsedTime(&c, b->ev[1], b->ev[2]));
+  if (march_ms) *march_ms = a;
+  if (composite_ms) *composite_ms = c;
+  return DPR_OK;
 }
 
 dpr_status dpr_set_batch_tile(dpr_world w, int32_t tw, int32_t th) {

@@ -684,6 +684,14 @@ dpr_status dpr_render_frame(dpr_world w, dpr_frame out) {
                 w->cam.width, w->cam.height);
   const int K = (int)w->bricks.size();
   if (K > kMaxFrags) return fail(DPR_ERR_UNSUPPORTED, "dpr_render_frame: %d bricks > %d", K, kMaxFrags);
+  if (out->dev != w->dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_frame: frame of another device");
+  bool mixed = false;
+  for (const auto& b : w->bricks) mixed |= b.dtype != w->bricks[0].dtype;
+  if (!(w->params.flags & DPR_FLAG_PLAIN) && !mixed) {
+    st = ensure_majorants(w);
+    if (st != DPR_OK) return st;
+    return render_frame_batched(w, out);
+  }
   bool resize = (int)w->partials.size() != K;
   for (auto f : w->partials) resize |= f->w != out->w || f->h != out->h;
   if (resize) {

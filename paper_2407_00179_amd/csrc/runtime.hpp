@@ -111,6 +111,7 @@ CamG make_cam(const dpr_camera& c);
 SceneG make_scene(const dpr_world_t* w);
 dpr_status check_camera(const dpr_camera* c);
 dpr_status ensure_majorants(dpr_world_t* w);
+dpr_status render_frame_batched(dpr_world w, dpr_frame out);
 dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out);
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
                       const std::vector<int32_t>& ids, CompTable** out);

@@ -131,3 +131,25 @@ def test_batch_against_oracle(gpu_lib, dpr):
         fin = np.isfinite(wz)
         assert np.array_equal(np.isfinite(gz), fin)
     w.release()
+
+
+def test_render_frame_paths_and_timings(gpu_lib, dpr):
+    """render_frame (batched by default) equals the plain per-brick path bit for bit,
+    and the in-graph HIP event timings are available afterwards."""
+    dims, vol, boxes, tf = _scene(np.float16)
+    prm = RenderParams(0.5, 0.99, 25.0)
+    cam = _cams(dims)[1]
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=8)
+    with pytest.raises(dpr.DprError):
+        w.batch_timings()
+    a = dpr.Frame(gpu_lib, cam.width, cam.height)
+    w.render_frame(a)
+    march_ms, comp_ms = w.batch_timings()
+    assert march_ms > 0 and comp_ms > 0
+    w.set_params(dpr.Params(0.5, 0.99, 8, dpr.FLAG_PLAIN))
+    b = dpr.Frame(gpu_lib, cam.width, cam.height)
+    w.render_frame(b)
+    ra, za, _ = frame_np(a)
+    rb, zb, _ = frame_np(b)
+    assert np.array_equal(ra, rb) and np.array_equal(za, zb)
+    w.release()
