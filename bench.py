@@ -242,6 +242,63 @@ def bench_cfg3(args, dpr, torch, dev):
     return r
 
 
+def bench_train(args, dpr, torch, dev):
+    """256^3 FP32 density grid + 256-entry TF as parameters, 16 cameras at 512x512:
+    the differentiable forward (with checkpoint stores) and the adjoint march."""
+    import ctypes as C
+    from paper_2407_00179_amd import _native as N
+    from synth import fibonacci_cameras, perturb_blobs
+    cfg = get_config("cfg4")
+    dims = cfg.dims
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+    tgt = make_volume_small(dims, perturb_blobs(blobs, cfg.seeds["perturb"]), cfg.seeds["volume"], cfg.noise_amp)
+    tf = make_tf(cfg.seeds["tf"])
+    cams = fibonacci_cameras(dims, cfg.n_cams, *cfg.image)
+    n, W, H = len(cams), cfg.image[0], cfg.image[1]
+    v = torch.tensor(vol, device=dev.torch_device)
+    vt = torch.tensor(tgt, device=dev.torch_device)
+    t = torch.tensor(tf, device=dev.torch_device)
+    ca = (N.Camera * n)(*[dpr.to_c_camera(c) for c in cams])
+    cp = dpr.Params(cfg.step_voxels, 1.0, 16, 0).c()
+    nb = C.c_size_t()
+    dpr.check(dpr.lib.dpr_train_workspace_size(N.I64x3(*dims), ca, n, cfg.step_voxels, C.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev.torch_device)
+    out = torch.empty((n, H, W, 4), device=dev.torch_device)
+    target = torch.empty_like(out)
+    depth = torch.empty((n, H, W), device=dev.torch_device)
+    gv = torch.zeros_like(v)
+    gt = torch.zeros_like(t)
+
+    def fwd(vol_t, img):
+        dpr.check(dpr.lib.dpr_render_train_forward(dev.h, C.c_void_p(vol_t.data_ptr()), N.I64x3(*dims),
+                                                   C.c_void_p(t.data_ptr()), t.shape[0], 0.0, 1.0, cfg.density,
+                                                   C.byref(cp), ca, n, C.c_void_p(img.data_ptr()),
+                                                   C.c_void_p(depth.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                                   nb.value))
+
+    fwd(vt, target)
+    fwd(v, out)
+    g = (2.0 / out.numel()) * (out - target)
+
+    def bwd():
+        dpr.check(dpr.lib.dpr_render_backward(dev.h, C.c_void_p(v.data_ptr()), N.I64x3(*dims),
+                                              C.c_void_p(t.data_ptr()), t.shape[0], 0.0, 1.0, cfg.density,
+                                              C.byref(cp), ca, n, C.c_void_p(g.data_ptr()),
+                                              C.c_void_p(ws.data_ptr()), nb.value, C.c_void_p(gv.data_ptr()),
+                                              C.c_void_p(gt.data_ptr())))
+
+    bwd()
+    torch.cuda.synchronize()
+    reps = max(3, args.steps // 2)
+    ms_f = _timed(torch, lambda: fwd(v, out), reps)
+    ms_b = _timed(torch, bwd, reps)
+    return dict(workload="256^3 FP32 density + 256x4 TF as parameters, 16 cameras x 512x512, step 0.5 voxel, "
+                         "ERT off, checkpoint every 64 segments",
+                ms_forward=ms_f, ms_backward=ms_b, bwd_fwd_ratio=ms_b / ms_f,
+                workspace_bytes=nb.value)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,7 +306,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batch,cfg3,composite128")
+    ap.add_argument("--sections", default="batch,cfg3,train,composite128")
     ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -327,6 +384,9 @@ def main():
     if "cfg3" in secs:
         log("GPU: 27-brick 16-camera batched workload")
         line["batch_cfg3"] = bench_cfg3(args, dpr, torch, dev)
+    if "train" in secs:
+        log("GPU: differentiable render forward/backward")
+        line["train_cfg4"] = bench_train(args, dpr, torch, dev)
     if "composite128" in secs:
         log("GPU: K=128 composite at 3840x2160")
         line["composite_k128"] = bench_composite128(args, dpr, torch, dev)

@@ -119,12 +119,13 @@ def forward_image(volume, dims, tf, params: RenderParams, cams, chunk=1 << 15):
     return np.stack(out)
 
 
-def loss_and_grad(volume, dims, tf, params: RenderParams, cams, target, chunk=4096, n_elems=None):
+def loss_and_grad(volume, dims, tf, params: RenderParams, cams, target, chunk=4096, n_elems=None, pixels=None):
     """L2 loss and its gradients (FP64).
 
-    ``target``: (ncam, H, W, 4).  ``n_elems`` overrides the mean's denominator
-    (default: every channel of every pixel of every camera).
-    Returns (loss, grad_volume (same shape as volume), grad_tf (N, 4), image).
+    ``target``: (ncam, H, W, 4), or per camera (P, 4) when ``pixels`` gives each
+    camera's (px, py) subset.  ``n_elems`` overrides the mean's denominator
+    (default: every target channel).
+    Returns (loss, grad_volume (same shape as volume), grad_tf (N, 4), images).
     """
     vol_flat = np.asarray(volume, dtype=np.float64).ravel()
     tf = np.asarray(tf, dtype=np.float64)
@@ -133,14 +134,20 @@ def loss_and_grad(volume, dims, tf, params: RenderParams, cams, target, chunk=40
     D = params.density
     gV = np.zeros_like(vol_flat)
     gT = np.zeros_like(tf)
-    target = np.asarray(target, dtype=np.float64)
+    if pixels is None:
+        target = np.asarray(target, dtype=np.float64)
+    else:
+        target = [np.asarray(t, dtype=np.float64) for t in target]
     if n_elems is None:
-        n_elems = target.size
+        n_elems = sum(np.size(t) for t in target)
     loss = 0.0
     images = []
     for ci, cam in enumerate(cams):
-        py, px = np.mgrid[0:cam.height, 0:cam.width]
-        px, py = px.ravel(), py.ravel()
+        if pixels is None:
+            py, px = np.mgrid[0:cam.height, 0:cam.width]
+            px, py = px.ravel(), py.ravel()
+        else:
+            px, py = (np.asarray(a) for a in pixels[ci])
         tgt = target[ci].reshape(-1, 4)
         img = np.empty((px.size, 4))
         for c0 in range(0, px.size, chunk):
@@ -166,5 +173,5 @@ def loss_and_grad(volume, dims, tf, params: RenderParams, cams, target, chunk=40
                 dtf = (tf[j + 1] - tf[j]) * slope_scale
                 g_v = np.where(inside, np.sum(g4 * dtf, axis=1), 0.0)
                 np.add.at(gV, idx.ravel(), (g_v[:, None] * wt).ravel())
-        images.append(img.reshape(cam.height, cam.width, 4))
-    return loss, gV.reshape(np.shape(volume)), gT, np.stack(images)
+        images.append(img.reshape(cam.height, cam.width, 4) if pixels is None else img)
+    return loss, gV.reshape(np.shape(volume)), gT, (np.stack(images) if pixels is None else images)

@@ -16,7 +16,8 @@ import numpy as np
 from . import _native as N
 from ._native import DprError, F16, F32, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, check, lib  # noqa: F401
 
-__all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_camera"]
+__all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_camera", "render_train",
+           "DprRenderFn"]
 
 
 def _torch():
@@ -224,3 +225,87 @@ def composite(dev: Device, parts, out: Frame, ids=None):
     fr = (C.c_void_p * k)(*[f.h.value for f in parts])
     idarr = None if ids is None else (C.c_int32 * k)(*[int(i) for i in ids])
     check(lib.dpr_composite(dev.h, fr, idarr, k, out.h))
+
+
+# ---------------------------------------------------------------- differentiable render
+def _cam_array(cams):
+    return (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])
+
+
+def _train_args(volume, tf):
+    torch = _torch()
+    assert volume.is_cuda and volume.dtype == torch.float32 and volume.is_contiguous()
+    assert tf.is_cuda and tf.dtype == torch.float32 and tf.is_contiguous() and tf.shape[-1] == 4
+    nz, ny, nx = volume.shape
+    return N.I64x3(nx, ny, nz)
+
+
+def _make_fn():
+    torch = _torch()
+
+    class DprRenderFn(torch.autograd.Function):
+        """Differentiable render of a whole FP32 volume with a TF table (ERT off, no skipping).
+
+        forward(volume (nz,ny,nx), tf (N,4), dev, cams, params, lo, hi, density) -> images (n,H,W,4).
+        backward runs the hand-written adjoint ray march (dpr_render_backward).
+        """
+
+        @staticmethod
+        def forward(ctx, volume, tf, dev, cams, params, lo, hi, density):
+            dims = _train_args(volume, tf)
+            ca = _cam_array(cams)
+            n, W, H = len(cams), int(cams[0].width), int(cams[0].height)
+            nbytes = C.c_size_t()
+            check(lib.dpr_train_workspace_size(dims, ca, n, float(params.step_voxels), C.byref(nbytes)))
+            ws = torch.empty(nbytes.value, dtype=torch.uint8, device=volume.device)
+            out = torch.empty((n, H, W, 4), dtype=torch.float32, device=volume.device)
+            depth = torch.empty((n, H, W), dtype=torch.float32, device=volume.device)
+            cp = params.c()
+            check(lib.dpr_render_train_forward(dev.h, C.c_void_p(volume.data_ptr()), dims, C.c_void_p(tf.data_ptr()),
+                                               tf.shape[0], lo, hi, density, C.byref(cp), ca, n,
+                                               C.c_void_p(out.data_ptr()), C.c_void_p(depth.data_ptr()),
+                                               C.c_void_p(ws.data_ptr()), nbytes.value))
+            ctx.save_for_backward(volume, tf)
+            ctx.ws, ctx.dev, ctx.cams, ctx.params, ctx.rng = ws, dev, cams, params, (lo, hi, density)
+            ctx.mark_non_differentiable(depth)
+            return out, depth
+
+        @staticmethod
+        def backward(ctx, g_out, g_depth):
+            volume, tf = ctx.saved_tensors
+            dims = _train_args(volume, tf)
+            ca = _cam_array(ctx.cams)
+            g = g_out.contiguous()
+            gv = torch.zeros_like(volume)
+            gt = torch.zeros_like(tf)
+            lo, hi, density = ctx.rng
+            cp = ctx.params.c()
+            check(lib.dpr_render_backward(ctx.dev.h, C.c_void_p(volume.data_ptr()), dims, C.c_void_p(tf.data_ptr()),
+                                          tf.shape[0], lo, hi, density, C.byref(cp), ca, len(ctx.cams),
+                                          C.c_void_p(g.data_ptr()), C.c_void_p(ctx.ws.data_ptr()), ctx.ws.numel(),
+                                          C.c_void_p(gv.data_ptr()), C.c_void_p(gt.data_ptr())))
+            return gv, gt, None, None, None, None, None, None
+
+    return DprRenderFn
+
+
+_FN = None
+
+
+def render_train(dev, volume, tf, cams, params=None, lo=0.0, hi=1.0, density=20.0):
+    """Images (n, H, W, 4) of ``volume`` seen by ``cams``, differentiable in volume and tf."""
+    global _FN
+    if _FN is None:
+        _FN = _make_fn()
+    params = params or Params(0.5, 1.0, 16, 0)
+    out, _ = _FN.apply(volume, tf, dev, cams, params, lo, hi, density)
+    return out
+
+
+def __getattr__(name):
+    if name == "DprRenderFn":
+        global _FN
+        if _FN is None:
+            _FN = _make_fn()
+        return _FN
+    raise AttributeError(name)

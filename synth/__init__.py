@@ -14,7 +14,7 @@ transparent regions, turbulence-like noise, non-cubic shapes and FP16 storage.
 """
 
 from .volume import (  # noqa: F401
-    BlobSet, make_blobs, blobs_field, white_noise, fbm_field, make_volume_small,
+    BlobSet, make_blobs, perturb_blobs, blobs_field, white_noise, fbm_field, make_volume_small,
     make_volume_large,
 )
 from .scene import (  # noqa: F401
