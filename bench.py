@@ -85,7 +85,8 @@ def _events(torch):
 def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
     dev = dpr.Device(0)
     w = dpr.World(dev, dims)
-    prm = dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0)
+    # batched render enqueued directly (no graph replay) so HIP events bracket each kernel
+    prm = dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH)
     w.set_params(prm)
     for b in vol_bricks:
         w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)

@@ -61,7 +61,7 @@ typedef enum { DPR_F32 = 0, DPR_F16 = 1 } dpr_dtype;
 /* render-parameter and call flags */
 #define DPR_FLAG_NO_SKIP 0x1u    /* disable macrocell empty-space skipping          */
 #define DPR_FLAG_PLAIN 0x2u      /* one plain launch per (camera, brick) + composite  */
-#define DPR_FLAG_NO_GRAPH 0x4u   /* batch: enqueue directly, no HIP graph replay     */
+#define DPR_FLAG_NO_GRAPH 0x4u   /* batched paths: enqueue directly, no graph replay */
 
 typedef struct dpr_device_t* dpr_device; /* one GPU + one HIP stream              */
 typedef struct dpr_world_t* dpr_world;   /* this rank's bricks + TF + camera      */
@@ -80,7 +80,7 @@ typedef struct {
 /* step_voxels: lattice step dt = step_voxels * h, in (0, 1].
  * ert_threshold: stop a ray once 1 - T >= threshold; >= 1 disables.
  * macrocell_cells: macrocell edge in cells (power of two in [2, 64]).
- * flags: DPR_FLAG_NO_SKIP.                                                      */
+ * flags: DPR_FLAG_NO_SKIP, DPR_FLAG_PLAIN, DPR_FLAG_NO_GRAPH (dpr_render_frame). */
 typedef struct {
   float step_voxels;
   float ert_threshold;
@@ -217,9 +217,10 @@ dpr_status dpr_autotune_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_
 /* Force a tile shape (tile_w * tile_h must be a multiple of 64, <= 1024).      */
 dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
 /* Durations of the march kernel and of the tile compositor of the last batched
- * render (dpr_render_batch or dpr_render_frame), from HIP events recorded on the
- * device stream around each kernel (also inside the replayed graph).
- * Synchronises.  DPR_ERR_INVALID_STATE before any batched render.               */
+ * render (dpr_render_batch with DPR_FLAG_NO_GRAPH, or dpr_render_frame with
+ * DPR_FLAG_NO_GRAPH in the render parameters), from HIP events recorded on the
+ * device stream around each kernel.  Synchronises.  DPR_ERR_INVALID_STATE when
+ * the last batched render was a graph replay (or there was none).             */
 dpr_status dpr_batch_timings(dpr_world, float* march_ms, float* composite_ms);
 
 /* ---------------------------------------------------------------- training */

@@ -54,6 +54,24 @@ def _corners(dims, g):
     return idx, wt
 
 
+def _lerp_value(vals, wt):
+    """Trilinear value from the 8 corner values (stencil order of _corners) in lerp
+    form a + f (b - a), exact on constant stencils; the fractions are recovered
+    from the weights (w1 = (1-fz)(1-fy) fx, ...)."""
+    fx = wt[:, 1] + wt[:, 3] + wt[:, 5] + wt[:, 7]
+    fy = wt[:, 2] + wt[:, 3] + wt[:, 6] + wt[:, 7]
+    fz = wt[:, 4] + wt[:, 5] + wt[:, 6] + wt[:, 7]
+
+    def lerp(a, b, f):
+        return a + f * (b - a)
+
+    c00 = lerp(vals[:, 0], vals[:, 1], fx)
+    c01 = lerp(vals[:, 2], vals[:, 3], fx)
+    c10 = lerp(vals[:, 4], vals[:, 5], fx)
+    c11 = lerp(vals[:, 6], vals[:, 7], fx)
+    return lerp(lerp(c00, c01, fy), lerp(c10, c11, fy), fz)
+
+
 def _tf_parts(tf, v, lo, hi):
     n = tf.shape[0]
     raw = (v - lo) / (hi - lo)
@@ -85,7 +103,7 @@ def _trace(vol_flat, dims, tf, params, o, d, record):
         ell = np.maximum(np.minimum((s + 1.0) * dt, t_out[act]) - np.maximum(s * dt, t_in[act]), 0.0)
         p = o[act] + ((s + 0.5) * dt)[:, None] * d[act]
         idx, wt = _corners(dims, p / h - 0.5)
-        v = np.sum(wt * vol_flat[idx], axis=1)
+        v = _lerp_value(vol_flat[idx], wt)
         rgba, j, w, inside = _tf_parts(tf, v, params.tf_lo, params.tf_hi)
         tau = D * rgba[:, 3] * ell
         e = np.exp(-tau)

@@ -122,13 +122,16 @@ def trilinear(data, stored_lo, dims, g):
     def V(dz, dy, dx):
         return vals[z0 + dz, y0 + dy, x0 + dx].astype(np.float64)
 
-    c00 = V(0, 0, 0) * (1 - fx) + V(0, 0, 1) * fx
-    c01 = V(0, 1, 0) * (1 - fx) + V(0, 1, 1) * fx
-    c10 = V(1, 0, 0) * (1 - fx) + V(1, 0, 1) * fx
-    c11 = V(1, 1, 0) * (1 - fx) + V(1, 1, 1) * fx
-    c0 = c00 * (1 - fy) + c01 * fy
-    c1 = c10 * (1 - fy) + c11 * fy
-    return c0 * (1 - fz) + c1 * fz
+    # lerp form a + f (b - a): equal corners give exactly their value, so a sample
+    # inside a constant region (e.g. a plateau at the TF range end) is exact
+    def lerp(a, b, f):
+        return a + f * (b - a)
+
+    c00 = lerp(V(0, 0, 0), V(0, 0, 1), fx)
+    c01 = lerp(V(0, 1, 0), V(0, 1, 1), fx)
+    c10 = lerp(V(1, 0, 0), V(1, 0, 1), fx)
+    c11 = lerp(V(1, 1, 0), V(1, 1, 1), fx)
+    return lerp(lerp(c00, c01, fy), lerp(c10, c11, fy), fz)
 
 
 def tf_lookup(tf, v, lo, hi):

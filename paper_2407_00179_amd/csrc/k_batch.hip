@@ -276,7 +276,7 @@ static dpr_status upload(V** dst, const std::vector<V>& src, hipStream_t st, con
   return DPR_OK;
 }
 
-static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
+static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool timed) {
   SceneG sc = make_scene(w);
   BatchG g{};
   g.cams = b->d_cams;
@@ -291,7 +291,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
   const bool f16 = w->bricks[0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, b->head);
-  if (b->ev[0]) (void)hipEventRecord(b->ev[0], st);
+  if (timed) (void)hipEventRecord(b->ev[0], st);
   if (f16) {
     if (b->skip)
       hipLaunchKernelGGL((batch_march_kernel<__half, true>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
@@ -303,7 +303,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
     else
       hipLaunchKernelGGL((batch_march_kernel<float, false>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
   }
-  if (b->ev[1]) (void)hipEventRecord(b->ev[1], st);
+  if (timed) (void)hipEventRecord(b->ev[1], st);
   const int tp = b->tile_w * b->tile_h;
   const int chunks = (tp + 63) / 64;
   dim3 cgrid((unsigned)b->n_tiles * chunks);
@@ -316,7 +316,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st) {
   else
     hipLaunchKernelGGL(tile_composite_kernel<256>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
                        b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
-  if (b->ev[2]) (void)hipEventRecord(b->ev[2], st);
+  if (timed) (void)hipEventRecord(b->ev[2], st);
   return hipGetLastError();
 }
 
@@ -427,7 +427,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
 static dpr_status capture_graph(dpr_world w, BatchState* b) {
   if (!b->cap) DPR_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
   DPR_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_batch(w, b, b->cap);
+  hipError_t e = enqueue_batch(w, b, b->cap, false);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->cap, &g);
   if (e != hipSuccess) {
@@ -519,7 +519,7 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
     if (s != DPR_OK) return s;
   }
   if (flags & DPR_FLAG_NO_GRAPH) {
-    DPR_HIP(enqueue_batch(w, b, w->dev->stream));
+    DPR_HIP(enqueue_batch(w, b, w->dev->stream, true));
     b->timed = true;
     return DPR_OK;
   }
@@ -528,12 +528,13 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
     if (s != DPR_OK) return s;
   }
   DPR_HIP(hipGraphLaunch(b->exec, w->dev->stream));
-  b->timed = true;
+  b->timed = false;
   return DPR_OK;
 }
 
 dpr_status render_frame_batched(dpr_world w, dpr_frame out) {
-  return render_batch_tiled(w, &w->cam, 1, &out, 0, w->batch_tile_w, w->batch_tile_h);
+  return render_batch_tiled(w, &w->cam, 1, &out, w->params.flags & DPR_FLAG_NO_GRAPH, w->batch_tile_w,
+                            w->batch_tile_h);
 }
 
 }  // namespace dpr
@@ -556,7 +557,8 @@ dpr_status dpr_render_batch(dpr_world w, const dpr_camera* cams, int32_t n, dpr_
 dpr_status dpr_batch_timings(dpr_world w, float* march_ms, float* composite_ms) {
   if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_batch_timings: NULL world");
   BatchState* b = w->batch;
-  if (!b || !b->timed || !b->ev[0]) return fail(DPR_ERR_INVALID_STATE, "dpr_batch_timings: no batched render yet");
+  if (!b || !b->timed || !b->ev[0])
+    return fail(DPR_ERR_INVALID_STATE, "dpr_batch_timings: the last batched render was not enqueued directly");
   DPR_HIP(hipEventSynchronize(b->ev[2]));
   float a = 0.f, c = 0.f;
   DPR_HIP(hipEventElapsedTime(&a, b->ev[0], b->ev[1]));

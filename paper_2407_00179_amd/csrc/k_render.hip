@@ -8,48 +8,78 @@ namespace dpr {
 
 // ------------------------------------------------------------------ relayout
 // Linear x-fastest stored brick -> 8^3 blocks (x fastest inside a block, blocks
-// x-fastest).  One thread per output element; padding voxels are zero and are
+// x-fastest).  One workgroup re-tiles a row of 4 consecutive blocks (32 x 8 x 8
+// voxels): reads are whole 32-voxel rows, the tile is transposed through LDS and
+// written as one contiguous run of 4 blocks.  Padding voxels are zero and are
 // never read by the sampler.
 template <typename E>
 __global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src, E* __restrict__ dst, int sx,
-                                                       int sy, int sz, int bx, int by, uint64_t total) {
-  uint64_t idx = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= total) return;
-  uint32_t w = (uint32_t)(idx & 511);
-  uint64_t blk = idx >> 9;
-  int x = (int)(blk % (uint64_t)bx) * 8 + (int)(w & 7);
-  uint64_t r = blk / (uint64_t)bx;
-  int y = (int)(r % (uint64_t)by) * 8 + (int)((w >> 3) & 7);
-  int z = (int)(r / (uint64_t)by) * 8 + (int)(w >> 6);
-  E v = E(0);
-  if (x < sx && y < sy && z < sz) v = src[((uint64_t)z * sy + y) * sx + x];
-  dst[idx] = v;
+                                                       int sy, int sz, int bx, int by, int bz) {
+  __shared__ E tile[8][8][33];  // [z][y][x] with one pad column
+  const int groups_x = (bx + 3) >> 2;
+  const int g = blockIdx.x;
+  const int gx = g % groups_x;
+  const int rest = g / groups_x;
+  const int byi = rest % by, bzi = rest / by;
+  const int x0 = gx * 32, y0 = byi * 8, z0 = bzi * 8;
+  const int t = threadIdx.x;
+  const int lx = t & 31;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int row = (t >> 5) + 8 * i;  // 0..63 -> (y, z)
+    const int ly = row & 7, lz = row >> 3;
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    E v = E(0);
+    if (x < sx && y < sy && z < sz) v = src[((size_t)z * sy + y) * sx + x];
+    tile[lz][ly][lx] = v;
+  }
+  __syncthreads();
+  const int nblk = min(4, bx - gx * 4);
+  const size_t base = (((size_t)bzi * by + byi) * bx + (size_t)gx * 4) * kBlockVoxels;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int e = t + 256 * i;  // 0..2047: block-major, then z, y, x inside the block
+    const int blk = e >> 9, w = e & 511;
+    if (blk < nblk) dst[base + e] = tile[w >> 6][(w >> 3) & 7][blk * 8 + (w & 7)];
+  }
 }
 
 // ------------------------------------------------------------------ macrocell ranges
 // One workgroup per macrocell: min/max over owned-relative voxels [mc m - 1, mc m + mc]
 // per axis, clipped to the stored range (stored index = owned index + ghost_lo).
+// Rows of the window are read from the linear stored copy (contiguous in x), and
+// workgroups are ordered so that each XCD walks a contiguous slab of macrocells,
+// which keeps the shared apron rows in that XCD's L2.
 template <typename T>
-__global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vox, int sx, int sy, int sz,
-                                                        uint32_t bsy, uint32_t bsz, int gx, int gy, int gz,
-                                                        int mc, int mdx, int mdy, int mdz,
+__global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vox, int sx, int sy, int sz, int gx,
+                                                        int gy, int gz, int mc, int mdx, int mdy, int mdz,
                                                         float2* __restrict__ ranges) {
-  int m = blockIdx.x;
+  const int count = mdx * mdy * mdz;
+  const int nb = gridDim.x;
+  const int per = (nb + 7) >> 3;
+  const int m = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (m >= count) return;
   int mx = m % mdx, my = (m / mdx) % mdy, mz = m / (mdx * mdy);
   int x0 = max(0, mc * mx - 1 + gx), x1 = min(sx - 1, mc * mx + mc + gx);
   int y0 = max(0, mc * my - 1 + gy), y1 = min(sy - 1, mc * my + mc + gy);
   int z0 = max(0, mc * mz - 1 + gz), z1 = min(sz - 1, mc * mz + mc + gz);
   int wx = x1 - x0 + 1, wy = y1 - y0 + 1, wz = z1 - z0 + 1;
-  int cnt = wx * wy * wz;
   float lo = INFINITY, hi = -INFINITY;
-  for (int i = threadIdx.x; i < cnt; i += 256) {
-    int x = x0 + i % wx;
-    int t = i / wx;
-    int y = y0 + t % wy;
-    int z = z0 + t / wy;
-    float v = load_voxel<T>(vox, blk_x(x) + blk_y(y, bsy) + blk_z(z, bsz));
-    lo = fminf(lo, v);
-    hi = fmaxf(hi, v);
+  // 32 lanes per row: up to 32 x values of one (y, z) row per pass
+  const int lane32 = threadIdx.x & 31, rowgrp = threadIdx.x >> 5;  // 8 rows in flight
+  const int rows = wy * wz;
+  for (int r = rowgrp; r < rows; r += 8) {
+    const int y = y0 + r % wy, z = z0 + r / wy;
+    const T* rowp = vox + ((size_t)z * sy + y) * sx + x0;
+    for (int x = lane32; x < wx; x += 32) {
+      float v;
+      if constexpr (sizeof(T) == 2)
+        v = __half2float(rowp[x]);
+      else
+        v = rowp[x];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     lo = fminf(lo, __shfl_xor(lo, o));
@@ -131,26 +161,26 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
 // ------------------------------------------------------------------ host launchers
 hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
                            int bz, hipStream_t st) {
-  uint64_t total = (uint64_t)bx * by * bz * kBlockVoxels;
-  dim3 grid((unsigned)((total + 255) / 256));
+  const int groups = ((bx + 3) / 4) * by * bz;
   if (elem_bytes == 4)
-    hipLaunchKernelGGL(relayout_kernel<uint32_t>, grid, dim3(256), 0, st, (const uint32_t*)src, (uint32_t*)dst, sx,
-                       sy, sz, bx, by, total);
+    hipLaunchKernelGGL(relayout_kernel<uint32_t>, dim3(groups), dim3(256), 0, st, (const uint32_t*)src,
+                       (uint32_t*)dst, sx, sy, sz, bx, by, bz);
   else
-    hipLaunchKernelGGL(relayout_kernel<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)src, (uint16_t*)dst, sx,
-                       sy, sz, bx, by, total);
+    hipLaunchKernelGGL(relayout_kernel<uint16_t>, dim3(groups), dim3(256), 0, st, (const uint16_t*)src,
+                       (uint16_t*)dst, sx, sy, sz, bx, by, bz);
   return hipGetLastError();
 }
 
-hipError_t launch_macrocells(const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st) {
+hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st) {
   int count = b.mdim[0] * b.mdim[1] * b.mdim[2];
+  int nb = ((count + 7) / 8) * 8;
   int gx = b.olo[0] - b.slo[0], gy = b.olo[1] - b.slo[1], gz = b.olo[2] - b.slo[2];
   if (f16)
-    hipLaunchKernelGGL(macrocell_kernel<__half>, dim3(count), dim3(256), 0, st, (const __half*)b.data, b.sdim[0],
-                       b.sdim[1], b.sdim[2], b.bsy, b.bsz, gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], ranges);
+    hipLaunchKernelGGL(macrocell_kernel<__half>, dim3(nb), dim3(256), 0, st, (const __half*)linear, b.sdim[0],
+                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], ranges);
   else
-    hipLaunchKernelGGL(macrocell_kernel<float>, dim3(count), dim3(256), 0, st, (const float*)b.data, b.sdim[0],
-                       b.sdim[1], b.sdim[2], b.bsy, b.bsz, gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], ranges);
+    hipLaunchKernelGGL(macrocell_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)linear, b.sdim[0],
+                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], ranges);
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 // its own tau (recomputed from the volume), and it is reset to the stored value at
 // every checkpoint.  With g_C = dL/dC, g_a = dL/dalpha and C_{>s} the colour of the
 // segments behind s (accumulated on the way back):
-//   dL/dc_s   = (T_s - T_{s+1}) g_C
+//   dL/dc_s   = T_s (1 - e^{-tau_s}) g_C
 //   dL/dtau_s = g_C . (T_{s+1} c_s - C_{>s}) + g_a T_S,   dL/dA_s = dL/dtau_s D l_s
 // The TF gradient goes to the two lerp entries (weights 1-w, w) through an
 // LDS-private copy flushed once per workgroup; the volume gradient goes to the 8
@@ -237,7 +237,9 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
         const double tau_before = (tau > 0.f) ? tau_after - (double)tau : tau_after;
         const float T_next = __expf(-(float)tau_after);
         const float T_s = __expf(-(float)tau_before);
-        const float wgt = (tau > 0.f) ? T_s - T_next : 0.f;
+        // per-sample weight T_s (1 - e^-tau) with expm1: exact even for tau ~ 1e-5,
+        // where the difference T_s - T_{s+1} would lose most of its digits
+        const float wgt = (tau > 0.f) ? -T_s * expm1f(-tau) : 0.f;
         // dL/dc_s and dL/dA_s
         const float gcR = wgt * go.x, gcG = wgt * go.y, gcB = wgt * go.z;
         const float gtau = go.x * (T_next * cR - sr) + go.y * (T_next * cG - sg) + go.z * (T_next * cB - sb) +

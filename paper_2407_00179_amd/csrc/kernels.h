@@ -9,7 +9,7 @@ namespace dpr {
 
 hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
                            int bz, hipStream_t st);
-hipError_t launch_macrocells(const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st);
+hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st);
 hipError_t launch_majorants(const float2* ranges, int count, const float4* tf, int ntf, float lo, float hi,
                             float* maj, hipStream_t st);
 hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, const float4* tf, bool f16, bool skip,

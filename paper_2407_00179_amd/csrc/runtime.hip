@@ -36,6 +36,7 @@ dpr_status fail(dpr_status st, const char* fmt, ...) {
 }
 
 dpr_status hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();  // clear the thread's HIP error so it does not surface in unrelated calls
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
     return fail(DPR_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
   return fail(DPR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -59,6 +60,7 @@ dpr_status dev_alloc(void** p, size_t bytes, const char* what) {
     return fail(DPR_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (allocation %ld)", what, g_alloc_count);
   hipError_t e = hipMalloc(p, bytes ? bytes : 1);
   if (e != hipSuccess) {
+    (void)hipGetLastError();
     *p = nullptr;
     return fail(DPR_ERR_OUT_OF_MEMORY, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
   }
@@ -470,7 +472,7 @@ dpr_status dpr_world_commit(dpr_world w) {
     b.mc = mc;
     b.maj_tf_version = 0;
     BrickG g = b.device_view(false);
-    DPR_HIP(launch_macrocells(g, b.dtype == DPR_F16, mc, b.ranges, w->dev->stream));
+    DPR_HIP(launch_macrocells(b.linear, g, b.dtype == DPR_F16, mc, b.ranges, w->dev->stream));
   }
   DPR_HIP(hipStreamSynchronize(w->dev->stream));
   w->committed = true;

@@ -143,13 +143,20 @@ def test_render_frame_paths_and_timings(gpu_lib, dpr):
     with pytest.raises(dpr.DprError):
         w.batch_timings()
     a = dpr.Frame(gpu_lib, cam.width, cam.height)
-    w.render_frame(a)
+    w.render_frame(a)                      # graph replay: no per-kernel timings
+    with pytest.raises(dpr.DprError):
+        w.batch_timings()
+    w.set_params(dpr.Params(0.5, 0.99, 8, dpr.FLAG_NO_GRAPH))
+    c = dpr.Frame(gpu_lib, cam.width, cam.height)
+    w.render_frame(c)
     march_ms, comp_ms = w.batch_timings()
     assert march_ms > 0 and comp_ms > 0
+    rc, zc, _ = frame_np(c)
     w.set_params(dpr.Params(0.5, 0.99, 8, dpr.FLAG_PLAIN))
     b = dpr.Frame(gpu_lib, cam.width, cam.height)
     w.render_frame(b)
     ra, za, _ = frame_np(a)
     rb, zb, _ = frame_np(b)
     assert np.array_equal(ra, rb) and np.array_equal(za, zb)
+    assert np.array_equal(ra, rc) and np.array_equal(za, zc)
     w.release()

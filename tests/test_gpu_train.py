@@ -73,9 +73,17 @@ def test_gradients_match_oracle_adjoint(gpu_lib, dpr, step):
         assert per <= 10 * REL_TOL
 
 
+def _linear_tf(n=256):
+    """A kink-free table (every channel affine in the value), so central differences
+    of the loss never straddle a slope change of the transfer function."""
+    u = np.arange(n) / (n - 1)
+    return np.stack([0.2 + 0.7 * u, 0.9 - 0.6 * u, 0.5 + 0.0 * u, 0.05 + 0.85 * u], axis=1).astype(np.float32)
+
+
 def test_gradients_match_finite_differences(gpu_lib, dpr):
     """Directional derivatives g.u against FP64 central differences of the oracle forward."""
-    dims, vol, tgt_vol, tf, cams = _problem(n_cams=2)
+    dims, vol, tgt_vol, _, cams = _problem(n_cams=2)
+    tf = _linear_tf()
     prm = RenderParams(0.5, 1.0, 15.0)
     target = oracle.forward_image(tgt_vol, dims, tf, prm, cams)
     _, _, gv, gt = _gpu_loss_grad(dpr, gpu_lib, vol, tf, cams, prm, target)
@@ -131,8 +139,10 @@ def test_backward_accumulates(gpu_lib, dpr):
         if rep == 0:
             once_v, once_t = gv.clone(), gt.clone()
     torch.cuda.synchronize()
-    assert torch.allclose(gv, 2 * once_v, rtol=1e-5, atol=1e-9)
-    assert torch.allclose(gt, 2 * once_t, rtol=1e-5, atol=1e-9)
+    # atomics sum in a different order each call: compare at FP32 rounding of the largest entry
+    assert torch.allclose(gv, 2 * once_v, rtol=1e-4, atol=1e-5 * float(once_v.abs().max()))
+    assert torch.allclose(gt, 2 * once_t, rtol=1e-4, atol=1e-5 * float(once_t.abs().max()))
+    assert float(once_v.abs().max()) > 0 and float(once_t.abs().max()) > 0
     with pytest.raises(dpr.DprError):   # workspace too small
         dpr.check(dpr.lib.dpr_render_backward(gpu_lib.h, C.c_void_p(v.data_ptr()), N.I64x3(*dims),
                                               C.c_void_p(t.data_ptr()), t.shape[0], 0.0, 1.0, 15.0, C.byref(cp), ca,
@@ -183,14 +193,25 @@ def test_cfg4_subgrid_finite_differences(gpu_lib, dpr):
     eps = 1e-4
     # perturb only voxels off the clamped plateaus (values 0 and 1 sit on TF-clamp kinks)
     free = (v64 > 1e-3) & (v64 < 1 - 1e-3)
-    for r in range(3):
+    def fd_at(u, e):
+        ip = oracle.render_image(v64 + e * u, dims, tf, prm, cam, px, py)[0]
+        im = oracle.render_image(v64 - e * u, dims, tf, prm, cam, px, py)[0]
+        # pixel-wise difference of squared errors, free of cancellation
+        return float(np.sum((ip - im) * (ip + im - 2 * tgt_img))) / (2 * e)
+
+    checked = 0
+    for r in range(4):
         u = np.zeros_like(v64)
         u[112:144, 112:144, 112:144] = rng.choice([-1.0, 1.0], size=(32, 32, 32))
         u *= free
-        ip = oracle.render_image(v64 + eps * u, dims, tf, prm, cam, px, py)[0]
-        im = oracle.render_image(v64 - eps * u, dims, tf, prm, cam, px, py)[0]
-        # pixel-wise difference of squared errors, free of cancellation
-        fd = float(np.sum((ip - im) * (ip + im - 2 * tgt_img))) / (2 * eps)
+        fd, fd2 = fd_at(u, eps), fd_at(u, eps / 2)
         an = float(np.sum(g * u))
-        log(f"  cfg4 FD dir {r}: fd {fd:.6e} analytic {an:.6e}")
-        assert abs(fd - an) <= REL_TOL * abs(fd) + 1e-7
+        # a sample whose TF coordinate crosses a knot of the table within +-eps makes
+        # the central difference depend on eps: such a direction is a kink, skipped
+        kink = abs(fd - fd2) > 0.25 * REL_TOL * abs(fd2)
+        log(f"  cfg4 FD dir {r}: fd {fd:.6e} (eps/2 {fd2:.6e}) analytic {an:.6e} kink={kink}")
+        if kink:
+            continue
+        checked += 1
+        assert abs(fd2 - an) <= REL_TOL * abs(fd2) + 1e-7
+    assert checked >= 2
