@@ -98,6 +98,7 @@ def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
     out = dpr.Frame(dev, W, H)
     total = _count_samples(dpr, dev, w, [cam], K)
     w.set_camera(cam)
+    tile = w.autotune_batch([cam], [out])   # the tile shape used by every later render
 
     def step():
         w.commit()                                        # relayout + macrocell ranges
@@ -132,7 +133,7 @@ def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
     live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
     comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
     ms_comp8 = _timed(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), max(3, args.steps))
-    res = dict(ms_per_step=ms_step, samples=total, march_ms=float(np.mean(march_ms)),
+    res = dict(ms_per_step=ms_step, samples=total, tile=tile, march_ms=float(np.mean(march_ms)),
                tile_comp_ms=float(np.mean(comp_ms)), ms_plain=ms_plain, ms_plain_march=ms_plain_march,
                comp8_ms=ms_comp8, comp_bytes=comp_bytes)
     w.release()
@@ -309,6 +310,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="batch,cfg3,train,composite128")
     ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
+    ap.add_argument("--main-steps", type=int, default=None, help="override --steps for the default workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -363,6 +365,7 @@ def main():
                      "kernel": "batch_march_kernel", "ms_per_launch": r["march_ms"],
                      "ops_per_sample": OPS_PER_SAMPLE},
         "phases_ms": {"batch_march": r["march_ms"], "tile_composite": r["tile_comp_ms"]},
+        "batch_tile": r["tile"],
         "plain_per_brick": {"ms_render_and_composite": r["ms_plain"], "ms_8_marches": r["ms_plain_march"],
                             "msamples": r["samples"] / r["ms_plain"] / 1e3,
                             "batched_speedup_march": r["ms_plain_march"] / r["march_ms"]},

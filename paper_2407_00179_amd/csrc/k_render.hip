@@ -45,56 +45,81 @@ __global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src
 }
 
 // ------------------------------------------------------------------ macrocell ranges
-// One workgroup per macrocell: min/max over owned-relative voxels [mc m - 1, mc m + mc]
-// per axis, clipped to the stored range (stored index = owned index + ghost_lo).
-// Rows of the window are read from the linear stored copy (contiguous in x), and
-// workgroups are ordered so that each XCD walks a contiguous slab of macrocells,
-// which keeps the shared apron rows in that XCD's L2.
+// Macrocell m covers owned-relative voxels [mc m - 1, mc m + mc] per axis, clipped to
+// the stored range (stored index = owned index + ghost_lo).  One workgroup builds a
+// run of up to (kMaxRow - 2) / mc macrocells along x for one (my, mz): its 4 waves
+// split the (y, z) rows of the window, each wave reads the rows' x-span from the
+// linear stored copy (coalesced) and keeps a per-x-column min/max in registers; the
+// columns are combined in LDS and reduced over each macrocell's x-window.  Each
+// element is read at most ((mc+2)/mc)^2 times in total (the y and z aprons).
+constexpr int kMaxRow = 2112;
+
 template <typename T>
 __global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vox, int sx, int sy, int sz, int gx,
                                                         int gy, int gz, int mc, int mdx, int mdy, int mdz,
-                                                        float2* __restrict__ ranges) {
-  const int count = mdx * mdy * mdz;
-  const int nb = gridDim.x;
-  const int per = (nb + 7) >> 3;
-  const int m = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (m >= count) return;
-  int mx = m % mdx, my = (m / mdx) % mdy, mz = m / (mdx * mdy);
-  int x0 = max(0, mc * mx - 1 + gx), x1 = min(sx - 1, mc * mx + mc + gx);
-  int y0 = max(0, mc * my - 1 + gy), y1 = min(sy - 1, mc * my + mc + gy);
-  int z0 = max(0, mc * mz - 1 + gz), z1 = min(sz - 1, mc * mz + mc + gz);
-  int wx = x1 - x0 + 1, wy = y1 - y0 + 1, wz = z1 - z0 + 1;
-  float lo = INFINITY, hi = -INFINITY;
-  // 32 lanes per row: up to 32 x values of one (y, z) row per pass
-  const int lane32 = threadIdx.x & 31, rowgrp = threadIdx.x >> 5;  // 8 rows in flight
-  const int rows = wy * wz;
-  for (int r = rowgrp; r < rows; r += 8) {
-    const int y = y0 + r % wy, z = z0 + r / wy;
-    const T* rowp = vox + ((size_t)z * sy + y) * sx + x0;
-    for (int x = lane32; x < wx; x += 32) {
-      float v;
-      if constexpr (sizeof(T) == 2)
-        v = __half2float(rowp[x]);
-      else
-        v = rowp[x];
-      lo = fminf(lo, v);
-      hi = fmaxf(hi, v);
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, o));
-    hi = fmaxf(hi, __shfl_xor(hi, o));
-  }
-  __shared__ float slo[4], shi[4];
-  if ((threadIdx.x & 63) == 0) {
-    slo[threadIdx.x >> 6] = lo;
-    shi[threadIdx.x >> 6] = hi;
+                                                        int per_chunk, int chunks, float2* __restrict__ ranges) {
+  __shared__ float col_lo[kMaxRow], col_hi[kMaxRow];
+  const int c = blockIdx.x % chunks;
+  const int my = (blockIdx.x / chunks) % mdy, mz = blockIdx.x / (chunks * mdy);
+  const int mx0 = c * per_chunk, mx1 = min(mdx, mx0 + per_chunk);
+  const int xs = max(0, mc * mx0 - 1 + gx), xe = min(sx - 1, mc * mx1 + gx);
+  const int wx = xe - xs + 1;
+  const int y0 = max(0, mc * my - 1 + gy), y1 = min(sy - 1, mc * my + mc + gy);
+  const int z0 = max(0, mc * mz - 1 + gz), z1 = min(sz - 1, mc * mz + mc + gz);
+  const int wy = y1 - y0 + 1, rows = wy * (z1 - z0 + 1);
+  for (int x = threadIdx.x; x < wx; x += 256) {
+    col_lo[x] = INFINITY;
+    col_hi[x] = -INFINITY;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    float a = fminf(fminf(slo[0], slo[1]), fminf(slo[2], slo[3]));
-    float b = fmaxf(fmaxf(shi[0], shi[1]), fmaxf(shi[2], shi[3]));
-    ranges[m] = make_float2(a, b);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int P = (kMaxRow + 63) / 64;  // x positions per lane
+  float lo[P], hi[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    lo[j] = INFINITY;
+    hi[j] = -INFINITY;
+  }
+  for (int r = wave; r < rows; r += 4) {
+    const int y = y0 + r % wy, z = z0 + r / wy;
+    const T* rowp = vox + ((size_t)z * sy + y) * sx + xs;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int x = lane + 64 * j;
+      if (x < wx) {
+        float v;
+        if constexpr (sizeof(T) == 2)
+          v = __half2float(rowp[x]);
+        else
+          v = rowp[x];
+        lo[j] = fminf(lo[j], v);
+        hi[j] = fmaxf(hi[j], v);
+      }
+    }
+  }
+  // combine the 4 waves' columns in LDS, one wave at a time
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int x = lane + 64 * j;
+        if (x < wx) {
+          col_lo[x] = fminf(col_lo[x], lo[j]);
+          col_hi[x] = fmaxf(col_hi[x], hi[j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // reduce each macrocell's x-window [mc mx - 1, mc mx + mc] (stored coordinates)
+  for (int mx = mx0 + threadIdx.x; mx < mx1; mx += 256) {
+    const int a0 = max(0, mc * mx - 1 + gx) - xs, a1 = min(sx - 1, mc * mx + mc + gx) - xs;
+    float a = INFINITY, b = -INFINITY;
+    for (int x = a0; x <= a1; ++x) {
+      a = fminf(a, col_lo[x]);
+      b = fmaxf(b, col_hi[x]);
+    }
+    ranges[((size_t)mz * mdy + my) * mdx + mx] = make_float2(a, b);
   }
 }
 
@@ -104,6 +129,9 @@ __global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vo
 __global__ __launch_bounds__(256) void majorant_kernel(const float2* __restrict__ ranges, int count,
                                                        const float4* __restrict__ tf, int ntf, float tf_lo,
                                                        float tf_hi, float* __restrict__ maj) {
+  __shared__ float alpha[kMaxTF];
+  for (int i = threadIdx.x; i < ntf; i += 256) alpha[i] = tf[i].w;
+  __syncthreads();
   int m = blockIdx.x * 256 + threadIdx.x;
   if (m >= count) return;
   float2 r = ranges[m];
@@ -117,7 +145,7 @@ __global__ __launch_bounds__(256) void majorant_kernel(const float2* __restrict_
   int e0 = max((int)floorf(xa) - 1, 0);
   int e1 = min((int)ceilf(xb) + 1, ntf - 1);
   float a = 0.f;
-  for (int e = e0; e <= e1; ++e) a = fmaxf(a, tf[e].w);
+  for (int e = e0; e <= e1; ++e) a = fmaxf(a, alpha[e]);
   maj[m] = a;
 }
 
@@ -172,15 +200,18 @@ hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, i
 }
 
 hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st) {
-  int count = b.mdim[0] * b.mdim[1] * b.mdim[2];
-  int nb = ((count + 7) / 8) * 8;
   int gx = b.olo[0] - b.slo[0], gy = b.olo[1] - b.slo[1], gz = b.olo[2] - b.slo[2];
+  const int per_chunk = (kMaxRow - 2) / mc;
+  const int chunks = (b.mdim[0] + per_chunk - 1) / per_chunk;
+  dim3 grid(chunks * b.mdim[1] * b.mdim[2]);
   if (f16)
-    hipLaunchKernelGGL(macrocell_kernel<__half>, dim3(nb), dim3(256), 0, st, (const __half*)linear, b.sdim[0],
-                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], ranges);
+    hipLaunchKernelGGL(macrocell_kernel<__half>, grid, dim3(256), 0, st, (const __half*)linear, b.sdim[0],
+                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], per_chunk, chunks,
+                       ranges);
   else
-    hipLaunchKernelGGL(macrocell_kernel<float>, dim3(nb), dim3(256), 0, st, (const float*)linear, b.sdim[0],
-                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], ranges);
+    hipLaunchKernelGGL(macrocell_kernel<float>, grid, dim3(256), 0, st, (const float*)linear, b.sdim[0],
+                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], per_chunk, chunks,
+                       ranges);
   return hipGetLastError();
 }
 

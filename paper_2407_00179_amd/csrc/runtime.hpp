@@ -102,7 +102,7 @@ struct dpr_world_t {
   std::vector<dpr_frame> partials;
   dpr::BatchState* batch = nullptr;
   uint64_t version = 1;  // bumped by commit, TF and parameter changes (invalidates batch graphs)
-  int batch_tile_w = 16, batch_tile_h = 16;
+  int batch_tile_w = 8, batch_tile_h = 8;
 };
 
 namespace dpr {
