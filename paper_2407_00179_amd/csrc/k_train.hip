@@ -175,6 +175,16 @@ __device__ __forceinline__ void flush_corners(float* __restrict__ gvol, const Tr
     if (acc[c] != 0.f) atomicAdd(gvol + b + off[c], acc[c]);
 }
 
+// TF-gradient replicas in LDS: lanes add into replica (lane & 7); replicas are
+// padded by one float so the same entry of different replicas falls in different
+// banks.  This cuts same-address atomic conflicts (many lanes hit the same few
+// entries, e.g. the transparent floor) by 8x.
+constexpr int kTfRep = 8;
+
+__device__ __forceinline__ void lds_add(float* p, float v) {
+  if (v != 0.f) atomicAdd(p, v);
+}
+
 __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const CamG* __restrict__ cams,
                                                              const float* __restrict__ vol,
                                                              const float4* __restrict__ tf,
@@ -185,9 +195,10 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
   extern __shared__ float4 lds[];
   float4* tfb = lds;
   float4* tfs = lds + g.ntf;
-  float* gt = (float*)(lds + 2 * g.ntf);  // 4 * ntf floats
+  float* gt = (float*)(lds + 2 * g.ntf);  // kTfRep replicas of 4 * ntf floats, stride 4 * ntf + 1
+  const int rstride = 4 * g.ntf + 1;
   stage_tf(tf, g.ntf, tfb, tfs, threadIdx.x, 256);
-  for (int i = threadIdx.x; i < 4 * g.ntf; i += 256) gt[i] = 0.f;
+  for (int i = threadIdx.x; i < kTfRep * rstride; i += 256) gt[i] = 0.f;
   __syncthreads();
   const int cam_id = blockIdx.x / tiles_per_cam;
   const int tile = blockIdx.x % tiles_per_cam;
@@ -195,6 +206,7 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
   const int px = (tile % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
   const int py = (tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
   const float slope_scale = g.tf_scale;
+  float* my_gt = gt + (lane & (kTfRep - 1)) * rstride;
   if (px < g.W && py < g.H) {
     const CamG& cam = cams[cam_id];
     const size_t ray = ((size_t)cam_id * g.H + py) * g.W + px;
@@ -210,15 +222,16 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
       const float Ddt = g.density * g.dt_f;
       float sr = 0.f, sg = 0.f, sb = 0.f;  // C_{>s}
       double tau_after = tau_total;
+      float T_next = T_S;  // transmittance after the current segment
       Stencil cur;
       cur.i = -1;
       float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       for (int s = r.s1; s >= r.s0; --s) {
         const int k = s - r.s0;
         // top of a chunk: optical depth after this segment from the forward's record
-        if (((k + 1) & (kCkpt - 1)) == 0 || s == r.s1) {
-          const int next = k + 1;
-          if (s != r.s1) tau_after = w[1 + next / kCkpt];
+        if (((k + 1) & (kCkpt - 1)) == 0 && s != r.s1) {
+          tau_after = w[1 + (k + 1) / kCkpt];
+          T_next = __expf(-(float)tau_after);
         }
         int64_t p[3];
 #pragma unroll
@@ -234,12 +247,15 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
         const float cR = fmaf(wl, ts.x, tb.x), cG = fmaf(wl, ts.y, tb.y), cB = fmaf(wl, ts.z, tb.z);
         const float Dl = (s == r.s0) ? r.dl_first : ((s == r.s1) ? r.dl_last : Ddt);
         const float tau = Dl * A;
-        const double tau_before = (tau > 0.f) ? tau_after - (double)tau : tau_after;
-        const float T_next = __expf(-(float)tau_after);
-        const float T_s = __expf(-(float)tau_before);
-        // per-sample weight T_s (1 - e^-tau) with expm1: exact even for tau ~ 1e-5,
-        // where the difference T_s - T_{s+1} would lose most of its digits
-        const float wgt = (tau > 0.f) ? -T_s * expm1f(-tau) : 0.f;
+        float T_s = T_next, wgt = 0.f;
+        double tau_before = tau_after;
+        if (tau > 0.f) {
+          tau_before = tau_after - (double)tau;
+          T_s = __expf(-(float)tau_before);
+          // per-sample weight T_s (1 - e^-tau) with expm1: exact even for tau ~ 1e-5,
+          // where the difference T_s - T_{s+1} would lose most of its digits
+          wgt = -T_s * expm1f(-tau);
+        }
         // dL/dc_s and dL/dA_s
         const float gcR = wgt * go.x, gcG = wgt * go.y, gcB = wgt * go.z;
         const float gtau = go.x * (T_next * cR - sr) + go.y * (T_next * cG - sg) + go.z * (T_next * cB - sb) +
@@ -249,17 +265,20 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
         sg = fmaf(wgt, cG, sg);
         sb = fmaf(wgt, cB, sb);
         tau_after = tau_before;
-        // TF entries j, j+1
-        float* e0 = gt + 4 * j;
+        T_next = T_s;
+        // TF entries j, j+1 (colour terms vanish where the sample is transparent)
+        float* e0 = my_gt + 4 * j;
         const float w0 = 1.f - wl;
-        atomicAdd(e0 + 0, w0 * gcR);
-        atomicAdd(e0 + 1, w0 * gcG);
-        atomicAdd(e0 + 2, w0 * gcB);
-        atomicAdd(e0 + 3, w0 * gA);
-        atomicAdd(e0 + 4, wl * gcR);
-        atomicAdd(e0 + 5, wl * gcG);
-        atomicAdd(e0 + 6, wl * gcB);
-        atomicAdd(e0 + 7, wl * gA);
+        if (wgt != 0.f) {
+          lds_add(e0 + 0, w0 * gcR);
+          lds_add(e0 + 1, w0 * gcG);
+          lds_add(e0 + 2, w0 * gcB);
+          lds_add(e0 + 4, wl * gcR);
+          lds_add(e0 + 5, wl * gcG);
+          lds_add(e0 + 6, wl * gcB);
+        }
+        lds_add(e0 + 3, w0 * gA);
+        lds_add(e0 + 7, wl * gA);
         // sample value: zero outside the TF range (clamped u)
         const bool inside = xr >= 0.f && xr <= (float)(g.ntf - 1);
         const float gv = inside ? (gA * ts.w + gcR * ts.x + gcG * ts.y + gcB * ts.z) * slope_scale : 0.f;
@@ -285,7 +304,9 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 4 * g.ntf; i += 256) {
-    const float v = gt[i];
+    float v = 0.f;
+#pragma unroll
+    for (int rep = 0; rep < kTfRep; ++rep) v += gt[rep * rstride + i];
     if (v != 0.f) atomicAdd(gtf + i, v);
   }
 }
@@ -425,7 +446,7 @@ dpr_status dpr_render_backward(dpr_device dev, const float* volume, const int64_
   if ((s = cam_table(dev, cams, n, &dc)) != DPR_OK) return s;
   const int tx = (g.W + 15) / 16, ty = (g.H + 15) / 16;
   dim3 grid((unsigned)(tx * ty * n));
-  size_t lds = 2 * sizeof(float4) * (size_t)n_tf + 4 * sizeof(float) * (size_t)n_tf;
+  size_t lds = 2 * sizeof(float4) * (size_t)n_tf + sizeof(float) * (size_t)kTfRep * (4 * n_tf + 1);
   hipLaunchKernelGGL(train_backward_kernel, grid, dim3(256), lds, dev->stream, g, dc, volume, (const float4*)tf,
                      (const float4*)grad_rgba, (const double*)ws, grad_volume, grad_tf, tx, tx * ty);
   DPR_HIP(hipGetLastError());
