@@ -23,7 +23,9 @@ struct CompTable {
   const float* depth[kMaxFrags];
   int idrank[kMaxFrags];
 };
+// fix_count / fix_list: device scratch for pixels whose fragments break the tile
+// order (fix_list holds n_pixels ints); fix_grid: workgroups of the fix-up pass.
 hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
-                            hipStream_t st);
+                            int* fix_count, int* fix_list, int fix_grid, hipStream_t st);
 
 }  // namespace dpr

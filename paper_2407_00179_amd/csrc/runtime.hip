@@ -237,7 +237,22 @@ dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_
   CompTable* tab = nullptr;
   dpr_status st = comp_table(dev, rg, dp, id, &tab);
   if (st != DPR_OK) return st;
-  DPR_HIP(launch_composite(tab, k, out->w * out->h, (float4*)out->rgba, out->depth, dev->stream));
+  const size_t P = (size_t)out->w * out->h;
+  if (!dev->fix_count) {
+    st = dev_alloc((void**)&dev->fix_count, sizeof(int), "composite fix-up counter");
+    if (st != DPR_OK) return st;
+  }
+  if (dev->fix_cap < P) {
+    DPR_HIP(hipStreamSynchronize(dev->stream));
+    dev_free(dev->fix_list);
+    dev->fix_list = nullptr;
+    dev->fix_cap = 0;
+    st = dev_alloc((void**)&dev->fix_list, P * sizeof(int), "composite fix-up list");
+    if (st != DPR_OK) return st;
+    dev->fix_cap = P;
+  }
+  DPR_HIP(launch_composite(tab, k, (int)P, (float4*)out->rgba, out->depth, dev->fix_count, dev->fix_list,
+                           dev->cu_count * 4, dev->stream));
   return DPR_OK;
 }
 
@@ -302,6 +317,8 @@ void dpr_device_release(dpr_device d) {
     dev_free(kv.second.dev);
     (void)hipHostFree(kv.second.host);
   }
+  dev_free(d->fix_count);
+  dev_free(d->fix_list);
   delete d;
 }
 

@@ -124,3 +124,39 @@ def test_composite_k128_full_hd_sampled(gpu_lib, dpr):
     assert np.array_equal(gz, wz.astype(np.float32).astype(np.float64))
     del rgba, depth, frames
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("K,W,H", [(8, 200, 100), (37, 64, 64), (128, 96, 80), (256, 40, 30)])
+def test_composite_out_of_tile_order(gpu_lib, dpr, K, W, H):
+    """Per-pixel random depths: most pixels break their tile's order and go through
+    the general per-wave sort; results must match the oracle and stay bitwise equal
+    under input permutation."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(K)
+    depth = (torch.rand((K, H, W), generator=g) * 5 + 0.5).to(gpu_lib.torch_device)
+    empty = (torch.rand((K, H, W), generator=g) < 0.3).to(gpu_lib.torch_device)
+    depth[empty] = float("inf")
+    a = (torch.rand((K, H, W), generator=g) * 0.6).to(gpu_lib.torch_device)
+    col = torch.rand((K, H, W, 3), generator=g).to(gpu_lib.torch_device)
+    rgba = torch.cat([col * a[..., None], a[..., None]], dim=-1)
+    rgba[empty] = 0.0
+    rgba = rgba.contiguous()
+    depth = depth.contiguous()
+    # a band of rows keeps one global order (fast path) next to the shuffled rest
+    depth[:, : H // 4] = torch.where(torch.isfinite(depth[:, : H // 4]),
+                                     torch.arange(K, device=gpu_lib.torch_device, dtype=torch.float32)[:, None, None]
+                                     + 1.0, depth[:, : H // 4])
+    frames = [dpr.Frame(gpu_lib, W, H, rgba=rgba[k], depth=depth[k]) for k in range(K)]
+    ids = np.random.default_rng(K).permutation(K)
+    out = dpr.Frame(gpu_lib, W, H)
+    dpr.composite(gpu_lib, frames, out, ids=ids)
+    got, gz, _ = frame_np(out)
+    want, wz = _oracle(rgba, depth, ids)
+    err = np.max(np.abs(got - want))
+    log(f"composite out-of-order K={K}: max err {err:.3e}")
+    assert err <= 2e-6 * max(1, K / 8)
+    assert np.array_equal(gz, wz.astype(np.float32).astype(np.float64))
+    perm = np.random.default_rng(1).permutation(K)
+    dpr.composite(gpu_lib, [frames[i] for i in perm], out, ids=ids[perm])
+    got2, gz2, _ = frame_np(out)
+    assert np.array_equal(got, got2) and np.array_equal(gz, gz2)
