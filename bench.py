@@ -310,7 +310,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="batch,cfg3,train,composite128")
     ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
-    ap.add_argument("--main-steps", type=int, default=None, help="override --steps for the default workload")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device-to-device copy first (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -339,6 +340,13 @@ def main():
 
     import torch
     import paper_2407_00179_amd as dpr
+    if args.copy_calibration:
+        x = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del x, y
     log("GPU: default workload")
     dev, r = bench_main(args, dpr, torch, bricks, dims, tf, cfg, cam)
     msamples = r["samples"] / (r["ms_per_step"] / 1e3) / 1e6

@@ -1,18 +1,21 @@
 // Sort-last compositor over K whole frames (dpr_composite).
 //
-// Fast path (one wave per 64 consecutive pixels, 4 waves per workgroup):
-//   pass 1  read every source's depth for the 64 pixels (coalesced) and take the
-//           nearest depth of each source over the tile with a wave reduction;
-//   order   rank the sources by (nearest depth, id rank) -- the tile order;
-//   pass 2  walk the sources in tile order, re-reading each lane's depth (now an
-//           L2 / Infinity Cache hit) and fetching RGBA only for live fragments, and
-//           composite front to back on the fly while checking, per pixel, that its
-//           live fragments really arrive in (depth, id) order.
+// Fast path: a workgroup of 4 waves walks a run of 256-pixel strips, each wave
+// taking one 64-pixel tile of every strip, so the four waves read neighbouring
+// bytes of every source.  Per tile the wave ranks the sources by (key, id rank)
+// -- the tile order -- where a source's key is its nearest depth over the last
+// tile of the run in which it had fragments (a sampled nearest depth over the
+// whole frame before that).  It then walks the sources in tile order, reading each
+// lane's depth (coalesced) and RGBA only for live fragments, and composites front
+// to back on the fly while checking, per pixel, that its live fragments really
+// arrive in (depth, id) order.  Every depth and every live RGBA is read once.
 // Neighbouring pixels almost always share one order (convex bricks: a separating
 // plane orders two bricks identically for every ray; per-rank depth slabs), so
 // nothing is stored per pixel and no LDS staging limits occupancy.  A pixel whose
-// fragments break the tile order is appended to a fix-up list and recomposited by
-// the fully general per-wave sort (composite_wave), which gives the same bits.
+// fragments break the tile order is recomposited in exact (depth, id) order with
+// the same arithmetic, so it gets the same bits: for up to 16 sources in place, by
+// repeated selection of its next fragment; for more, through a fix-up list that a
+// second pass works off with the fully general per-wave sort (composite_wave).
 #include "composite.h"
 #include "device_common.h"
 #include "kernels.h"
@@ -25,14 +28,70 @@ __device__ __forceinline__ float wave_min(float v) {
   return v;
 }
 
-template <int KMAX>
-__global__ __launch_bounds__(256) void composite_fast_kernel(const CompTable* __restrict__ tab, int K, int P,
+// Sampled nearest depth of every source over about kPriorTiles 64-pixel tiles
+// spread evenly over the frame (an odd tile stride, so the samples also spread
+// over the columns).  Block (s, k) reduces its slice of the samples of source k
+// into prior[k * kPriorSlices + s].
+constexpr int kPriorSlices = 4;
+constexpr int kPriorTiles = 512;
+
+__device__ __forceinline__ int prior_stride(int n_tiles) { return (n_tiles / kPriorTiles) | 1; }
+
+__global__ __launch_bounds__(256) void composite_prior_kernel(const CompTable* __restrict__ tab, int P,
+                                                              float* __restrict__ prior) {
+  __shared__ float wmin[4];
+  const int k = blockIdx.y, slice = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float* __restrict__ d = tab->depth[k];
+  const int n_tiles = (P + 63) / 64;
+  const int stride = prior_stride(n_tiles);
+  const int n_samp = (n_tiles + stride - 1) / stride;
+  constexpr int step = kPriorSlices * 4;
+  float m = INFINITY;
+  for (int j0 = slice + kPriorSlices * wave; j0 < n_samp; j0 += step * 8) {
+    float z[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * step;
+      const int p = j * stride * 64 + lane;
+      z[u] = (j < n_samp && p < P) ? d[p] : INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fminf(m, z[u]);
+  }
+  m = wave_min(m);
+  if (lane == 0) wmin[wave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    prior[k * kPriorSlices + slice] = fminf(fminf(wmin[0], wmin[1]), fminf(wmin[2], wmin[3]));
+}
+
+// Minimum over the 64 lanes with DPP row shifts and row broadcasts (VALU only);
+// the result is wave-uniform.
+#define DPR_DPP_MIN(v, ctrl, row_mask)                                                                        \
+  v = fminf(v, __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), ctrl, row_mask, \
+                                                          0xf, false)))
+__device__ __forceinline__ float wave_min_dpp(float v) {
+  DPR_DPP_MIN(v, 0x111, 0xf);  // row_shr:1
+  DPR_DPP_MIN(v, 0x112, 0xf);  // row_shr:2
+  DPR_DPP_MIN(v, 0x114, 0xf);  // row_shr:4
+  DPR_DPP_MIN(v, 0x118, 0xf);  // row_shr:8 -> lane 15 of each row holds the row minimum
+  DPR_DPP_MIN(v, 0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+  DPR_DPP_MIN(v, 0x143, 0xc);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the minimum
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+#undef DPR_DPP_MIN
+
+template <int KMAX, int B, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void composite_fast_kernel(const CompTable* __restrict__ tab, int K, int P,
+                                                             const float* __restrict__ prior,
                                                              float4* __restrict__ out_rgba,
                                                              float* __restrict__ out_depth, int* __restrict__ fix_count,
-                                                             int* __restrict__ fix_list) {
+                                                             int* __restrict__ fix_list, int strips_per_group) {
   __shared__ const float4* prgba[KMAX];
   __shared__ const float* pdepth[KMAX];
   __shared__ int prank[KMAX];
+  __shared__ float key0[KMAX];
   __shared__ float rep[4][KMAX];
   __shared__ unsigned char order[4][KMAX];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -40,100 +99,187 @@ __global__ __launch_bounds__(256) void composite_fast_kernel(const CompTable* __
     prgba[k] = tab->rgba[k];
     pdepth[k] = tab->depth[k];
     prank[k] = tab->idrank[k];
-  }
-  for (int k = lane; k < K; k += 64) order[wave][k] = (unsigned char)k;
-  __syncthreads();
-  const int p = (blockIdx.x * 4 + wave) * 64 + lane;
-  const bool live_px = p < P;
-  constexpr int B = KMAX < 16 ? KMAX : 16;
-  // pass 1: nearest depth of each source over the tile
-  for (int k0 = 0; k0 < K; k0 += B) {
-    float z[B];
+    float m = prior[k * kPriorSlices];
 #pragma unroll
-    for (int u = 0; u < B; ++u) z[u] = (live_px && k0 + u < K) ? pdepth[k0 + u][p] : INFINITY;
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const float m = wave_min(z[u]);
-      if (lane == 0 && k0 + u < K) rep[wave][k0 + u] = m;
-    }
+    for (int s = 1; s < kPriorSlices; ++s) m = fminf(m, prior[k * kPriorSlices + s]);
+    key0[k] = m;
   }
   __syncthreads();
-  // tile order by (nearest depth, id rank)
-  for (int k = lane; k < K; k += 64) {
-    const float rk = rep[wave][k];
-    const int ik = prank[k];
-    int r = 0;
-    for (int j = 0; j < K; ++j) {
-      const float rj = rep[wave][j];
-      r += (rj < rk) || (rj == rk && prank[j] < ik);
-    }
-    order[wave][r] = (unsigned char)k;
-  }
-  __syncthreads();
-  // pass 2: composite in tile order, checking the per-pixel order
-  float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f, zfirst = INFINITY;
-  float lz = -INFINITY;
-  int lr = -1;
-  bool bad = !live_px;
-  for (int i0 = 0; i0 < K; i0 += B) {
-    int ku[B];
-    float zu[B];
+  // the workgroup walks a run of 256-pixel strips, wave w taking the w-th 64-pixel
+  // tile of each strip, so the four waves read neighbouring bytes of every source
+  const int n_tiles = (P + 63) / 64;
+  const int n_strips = (n_tiles + 3) / 4;
+  const int s0 = blockIdx.x * strips_per_group;
+  const int s1 = min(n_strips, s0 + strips_per_group);
+  const int t0 = s0 * 4 + wave;
+  if (s0 >= s1 || t0 >= n_tiles) return;  // (no block-wide barrier follows)
+  // keys for the first tile: nearest depths over that tile, the sampled nearest
+  // depth for sources absent from it
+  {
+    const int p = t0 * 64 + lane;
+    for (int k0 = 0; k0 < K; k0 += B) {
+      float z[B];
 #pragma unroll
-    for (int u = 0; u < B; ++u) {
-      ku[u] = (i0 + u < K) ? order[wave][i0 + u] : 0;
-      zu[u] = (!bad && i0 + u < K) ? pdepth[ku[u]][p] : INFINITY;
-    }
-    float4 f[B];
+      for (int u = 0; u < B; ++u) z[u] = (p < P && k0 + u < K) ? pdepth[k0 + u][p] : INFINITY;
 #pragma unroll
-    for (int u = 0; u < B; ++u) f[u] = (zu[u] < INFINITY) ? prgba[ku[u]][p] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      if (zu[u] < INFINITY && !bad) {
-        const int r = prank[ku[u]];
-        if (zu[u] > lz || (zu[u] == lz && r > lr)) {
-          if (lr < 0) zfirst = zu[u];
-          cr = fmaf(tr, f[u].x, cr);
-          cg = fmaf(tr, f[u].y, cg);
-          cb = fmaf(tr, f[u].z, cb);
-          ca = fmaf(tr, f[u].w, ca);
-          tr *= 1.f - f[u].w;
-          lz = zu[u];
-          lr = r;
-        } else {
-          bad = true;  // out of tile order: the general sort takes this pixel
-        }
+      for (int u = 0; u < B; ++u) {
+        const float m = wave_min_dpp(z[u]);
+        if (lane == 0 && k0 + u < K) rep[wave][k0 + u] = m < INFINITY ? m : key0[k0 + u];
       }
     }
   }
-  if (live_px) {
-    if (bad) {
-      const int slot = atomicAdd(fix_count, 1);
-      fix_list[slot] = p;
-    } else {
-      out_rgba[p] = make_float4(cr, cg, cb, ca);
-      out_depth[p] = zfirst;
+  for (int t = t0; t < min(n_tiles, s1 * 4); t += 4) {
+    // tile order by (key, id rank); a source's key is its nearest depth over the
+    // last tile of the run where it had fragments (this tile, for the first one);
+    // any order gives the same bits, a good one just keeps pixels on the fast path
+    // (the previous tile's order is kept when the new keys leave it sorted)
+    bool sorted = t != t0;
+    if (sorted) {
+      for (int i = lane; i + 1 < K; i += 64) {
+        const int a = order[wave][i], b = order[wave][i + 1];
+        const float ka = rep[wave][a], kb = rep[wave][b];
+        sorted &= (ka < kb) || (ka == kb && prank[a] < prank[b]);
+      }
+      sorted = __all(sorted);
     }
+    if (!sorted) {
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // reads of the old order done before it is rewritten
+      for (int k = lane; k < K; k += 64) {
+        const float rk = rep[wave][k];
+        const int ik = prank[k];
+        int r = 0;
+        for (int j = 0; j < K; ++j) {
+          const float rj = rep[wave][j];
+          r += (rj < rk) || (rj == rk && prank[j] < ik);
+        }
+        order[wave][r] = (unsigned char)k;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // LDS writes visible to the whole wave
+    }
+    const int p = t * 64 + lane;
+    const bool live_px = p < P;
+    float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f, zfirst = INFINITY;
+    float lz = -INFINITY;
+    int lr = -1;
+    bool bad = !live_px;
+    // sources in batches of B: source indices and depths of a batch, then RGBA of
+    // its live fragments; the next batch's depths are requested before this batch
+    // is composited, so one memory round trip per batch is exposed
+    int ku[B];
+    float zu[B];
+    auto fetch = [&](int i1, int* kk, float* zz) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        kk[u] = (i1 + u < K) ? order[wave][i1 + u] : 0;
+        zz[u] = (live_px && i1 + u < K) ? pdepth[kk[u]][p] : INFINITY;
+      }
+    };
+    fetch(0, ku, zu);
+    for (int i0 = 0; i0 < K; i0 += B) {
+      float4 f[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        f[u] = (zu[u] < INFINITY && !bad) ? prgba[ku[u]][p] : make_float4(0.f, 0.f, 0.f, 0.f);
+      int kn[B];
+      float zn[B];
+      fetch(i0 + B, kn, zn);
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        // nearest depth of this source over the tile, the key for the next tiles
+        const float m = wave_min_dpp(zu[u]);
+        if (lane == 0 && i0 + u < K && m < INFINITY) rep[wave][ku[u]] = m;
+        if (zu[u] < INFINITY && !bad) {
+          const int r = prank[ku[u]];
+          if (zu[u] > lz || (zu[u] == lz && r > lr)) {
+            if (lr < 0) zfirst = zu[u];
+            cr = fmaf(tr, f[u].x, cr);
+            cg = fmaf(tr, f[u].y, cg);
+            cb = fmaf(tr, f[u].z, cb);
+            ca = fmaf(tr, f[u].w, ca);
+            tr *= 1.f - f[u].w;
+            lz = zu[u];
+            lr = r;
+          } else {
+            bad = true;  // out of tile order: the general sort takes this pixel
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        ku[u] = kn[u];
+        zu[u] = zn[u];
+      }
+    }
+    if constexpr (KMAX <= 16) {
+      // few sources: a pixel off the tile order is recomposited right here by
+      // repeatedly selecting its next fragment in (depth, id rank) order
+      if (live_px && bad) {
+        tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f, zfirst = INFINITY;
+        lz = -INFINITY;
+        lr = -1;
+        for (;;) {
+          float bz = INFINITY;
+          int br = 0x7fffffff, bk = -1;
+          for (int k = 0; k < K; ++k) {
+            const float z = pdepth[k][p];
+            const int r = prank[k];
+            if (z < INFINITY && (z > lz || (z == lz && r > lr)) && (z < bz || (z == bz && r < br))) {
+              bz = z;
+              br = r;
+              bk = k;
+            }
+          }
+          if (bk < 0) break;
+          const float4 f = prgba[bk][p];
+          if (lr < 0) zfirst = bz;
+          cr = fmaf(tr, f.x, cr);
+          cg = fmaf(tr, f.y, cg);
+          cb = fmaf(tr, f.z, cb);
+          ca = fmaf(tr, f.w, ca);
+          tr *= 1.f - f.w;
+          lz = bz;
+          lr = br;
+        }
+        bad = false;
+      }
+    }
+    if (live_px) {
+      if (bad) {
+        const int slot = atomicAdd(fix_count, 1);
+        fix_list[slot] = p;
+      } else {
+        out_rgba[p] = make_float4(cr, cg, cb, ca);
+        out_depth[p] = zfirst;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
 // General path for the pixels of the fix-up list: one wave per 64 listed pixels,
-// persistent over the list (its length is read on the device).
+// persistent over the list (its length is read on the device).  The last
+// workgroup to finish clears the list length and the finish count, so the
+// counters are zero again for the next call without a separate clear.
 template <int KMAX>
 __global__ __launch_bounds__(64) void composite_fixup_kernel(const CompTable* __restrict__ tab, int K,
                                                              float4* __restrict__ out_rgba,
                                                              float* __restrict__ out_depth,
-                                                             const int* __restrict__ fix_count,
+                                                             int* __restrict__ fix_count,
                                                              const int* __restrict__ fix_list) {
   __shared__ CompLDS<KMAX> s;
   __shared__ const float4* prgba[KMAX];
   __shared__ const float* pdepth[KMAX];
   const int lane = threadIdx.x;
-  for (int k = lane; k < K; k += 64) {
-    prgba[k] = tab->rgba[k];
-    pdepth[k] = tab->depth[k];
-  }
-  __syncthreads();
   const int n = *fix_count;
+  if (blockIdx.x * 64 < n) {
+    for (int k = lane; k < K; k += 64) {
+      prgba[k] = tab->rgba[k];
+      pdepth[k] = tab->depth[k];
+    }
+    __syncthreads();
+  }
   for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
     const bool live = base + lane < n;
     const int p = live ? fix_list[base + lane] : 0;
@@ -148,30 +294,47 @@ __global__ __launch_bounds__(64) void composite_fixup_kernel(const CompTable* __
     }
     __syncthreads();
   }
+  if (lane == 0) {
+    __threadfence();
+    if (atomicAdd(fix_count + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(fix_count, 0);
+      atomicExch(fix_count + 1, 0);
+    }
+  }
 }
 
-__global__ void zero_int_kernel(int* p) { *p = 0; }
+// Resident waves per SIMD of the fast kernel: the register budget that keeps
+// every workgroup of the persistent grid resident at once.
+constexpr int kFastWavesPerSimd = 5;
 
 template <int KMAX>
 static void launch_k(const CompTable* tab, int k, int n_pixels, float4* out_rgba, float* out_depth, int* fix_count,
-                     int* fix_list, int fix_grid, hipStream_t st) {
-  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, fix_count);
-  hipLaunchKernelGGL(composite_fast_kernel<KMAX>, dim3((n_pixels + 255) / 256), dim3(256), 0, st, tab, k, n_pixels,
-                     out_rgba, out_depth, fix_count, fix_list);
-  hipLaunchKernelGGL(composite_fixup_kernel<KMAX>, dim3(fix_grid), dim3(64), 0, st, tab, k, out_rgba, out_depth,
-                     fix_count, fix_list);
+                     int* fix_list, float* prior, int cu_count, hipStream_t st) {
+  if (n_pixels <= 0) return;
+  hipLaunchKernelGGL(composite_prior_kernel, dim3(kPriorSlices, k), dim3(256), 0, st, tab, n_pixels, prior);
+  // workgroups of 4 waves walk runs of 256-pixel strips, one resident grid
+  // (kFastWavesPerSimd workgroups per CU)
+  const int n_strips = (n_pixels + 255) / 256;
+  const int groups = cu_count * kFastWavesPerSimd;
+  const int per = (n_strips + groups - 1) / groups;
+  const int blocks = (n_strips + per - 1) / per;
+  hipLaunchKernelGGL((composite_fast_kernel<KMAX, 8, kFastWavesPerSimd>), dim3(blocks), dim3(256), 0, st, tab, k,
+                     n_pixels, prior, out_rgba, out_depth, fix_count, fix_list, per);
+  if constexpr (KMAX > 16)
+    hipLaunchKernelGGL(composite_fixup_kernel<KMAX>, dim3(cu_count), dim3(64), 0, st, tab, k, out_rgba, out_depth,
+                       fix_count, fix_list);
 }
 
 hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
-                            int* fix_count, int* fix_list, int fix_grid, hipStream_t st) {
+                            int* fix_count, int* fix_list, float* prior, int cu_count, hipStream_t st) {
   if (k <= 16)
-    launch_k<16>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, fix_grid, st);
+    launch_k<16>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, prior, cu_count, st);
   else if (k <= 64)
-    launch_k<64>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, fix_grid, st);
+    launch_k<64>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, prior, cu_count, st);
   else if (k <= 128)
-    launch_k<128>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, fix_grid, st);
+    launch_k<128>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, prior, cu_count, st);
   else
-    launch_k<256>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, fix_grid, st);
+    launch_k<256>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, prior, cu_count, st);
   return hipGetLastError();
 }
 

@@ -24,8 +24,11 @@ struct CompTable {
   int idrank[kMaxFrags];
 };
 // fix_count / fix_list: device scratch for pixels whose fragments break the tile
-// order (fix_list holds n_pixels ints); fix_grid: workgroups of the fix-up pass.
+// order (fix_count: two ints, zero on entry and left zero on exit; fix_list holds
+// n_pixels ints); prior: kCompPriorFloats floats of scratch for the sampled nearest
+// depth per source; cu_count: compute units of the device (sizes the grids).
+constexpr int kCompPriorFloats = kMaxFrags * 8;
 hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
-                            int* fix_count, int* fix_list, int fix_grid, hipStream_t st);
+                            int* fix_count, int* fix_list, float* prior, int cu_count, hipStream_t st);
 
 }  // namespace dpr

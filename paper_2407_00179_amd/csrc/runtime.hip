@@ -239,7 +239,13 @@ dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_
   if (st != DPR_OK) return st;
   const size_t P = (size_t)out->w * out->h;
   if (!dev->fix_count) {
-    st = dev_alloc((void**)&dev->fix_count, sizeof(int), "composite fix-up counter");
+    st = dev_alloc((void**)&dev->fix_count, 2 * sizeof(int), "composite fix-up counters");
+    if (st != DPR_OK) return st;
+    // zero once; the fix-up pass leaves both counters at zero after every call
+    DPR_HIP(hipMemsetAsync(dev->fix_count, 0, 2 * sizeof(int), dev->stream));
+  }
+  if (!dev->comp_prior) {
+    st = dev_alloc((void**)&dev->comp_prior, kCompPriorFloats * sizeof(float), "composite depth prior");
     if (st != DPR_OK) return st;
   }
   if (dev->fix_cap < P) {
@@ -252,7 +258,7 @@ dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_
     dev->fix_cap = P;
   }
   DPR_HIP(launch_composite(tab, k, (int)P, (float4*)out->rgba, out->depth, dev->fix_count, dev->fix_list,
-                           dev->cu_count * 4, dev->stream));
+                           dev->comp_prior, dev->cu_count, dev->stream));
   return DPR_OK;
 }
 
@@ -319,6 +325,7 @@ void dpr_device_release(dpr_device d) {
   }
   dev_free(d->fix_count);
   dev_free(d->fix_list);
+  dev_free(d->comp_prior);
   delete d;
 }
 

@@ -48,10 +48,12 @@ struct dpr_device_t {
   // composite tables keyed by (rgba ptr, depth ptr, id) of every part
   std::map<std::vector<uint64_t>, dpr::CompEntry> comp_cache;
   uint64_t use_clock = 0;
-  // compositor fix-up scratch: a counter and a list of up to fix_cap pixel indices
+  // compositor fix-up scratch: list length + finish count (both zero between calls)
+  // and a list of up to fix_cap pixel indices
   int* fix_count = nullptr;
   int* fix_list = nullptr;
   size_t fix_cap = 0;
+  float* comp_prior = nullptr;  // sampled nearest depth per source (kCompPriorFloats)
 };
 
 struct dpr_frame_t {
