@@ -182,8 +182,13 @@ struct BatchState {
   std::vector<dpr_frame> outs;
   std::vector<const void*> out_ptrs;
   int tile_w = 0, tile_h = 0;
-  uint64_t version = 0;
+  uint64_t geo_version = 0;
   bool skip = true;
+  // brick views last uploaded to d_bricks, and the scene arguments and TF table
+  // baked into the captured graph
+  std::vector<BrickG> h_bricks;
+  SceneG cap_scene{};
+  const float4* cap_tf = nullptr;
   // device data
   CamG* d_cams = nullptr;
   BrickG* d_bricks = nullptr;
@@ -221,6 +226,9 @@ struct BatchState {
     frag_rgba = nullptr;
     frag_depth = nullptr;
     head = nullptr;
+    drop_graph();
+  }
+  void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
@@ -335,7 +343,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   }
   b->tile_w = tw;
   b->tile_h = th;
-  b->version = w->version;
+  b->geo_version = w->geo_version;
   b->skip = !(w->params.flags & DPR_FLAG_NO_SKIP);
   const SceneG sc = make_scene(w);
   std::vector<CamG> cg(n);
@@ -395,6 +403,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   dpr_status s;
   if ((s = upload(&b->d_cams, cg, st, "batch cameras")) != DPR_OK) return s;
   if ((s = upload(&b->d_bricks, bg, st, "batch bricks")) != DPR_OK) return s;
+  b->h_bricks = bg;
   if ((s = upload(&b->d_items, items, st, "batch items")) != DPR_OK) return s;
   if ((s = upload(&b->d_tile_cam, tile_cam, st, "batch tile cameras")) != DPR_OK) return s;
   if ((s = upload(&b->d_tile_xy, tile_xy, st, "batch tile coordinates")) != DPR_OK) return s;
@@ -437,13 +446,41 @@ static dpr_status capture_graph(dpr_world w, BatchState* b) {
   if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
   b->graph = g;
   DPR_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  b->cap_scene = make_scene(w);
+  b->cap_tf = w->tf_dev;
+  return DPR_OK;
+}
+
+// The item lists depend only on geometry (bricks, cameras, tile shape); data
+// recommits and transfer-function changes only touch the brick views (device
+// pointers, macrocell grids) and the scene arguments, which are refreshed here
+// without rebuilding: brick views are re-uploaded when they changed, and the
+// captured graph is dropped when an argument baked into it changed.
+static dpr_status refresh_batch(dpr_world w, BatchState* b) {
+  std::vector<BrickG> bg;
+  for (const auto& br : w->bricks) bg.push_back(br.device_view(b->skip));
+  if (bg.size() != b->h_bricks.size() || memcmp(bg.data(), b->h_bricks.data(), bg.size() * sizeof(BrickG)) != 0) {
+    hipStream_t st = w->dev->stream;
+    DPR_HIP(hipStreamSynchronize(st));
+    b->drop_graph();
+    DPR_HIP(hipMemcpyAsync(b->d_bricks, bg.data(), bg.size() * sizeof(BrickG), hipMemcpyHostToDevice, st));
+    DPR_HIP(hipStreamSynchronize(st));
+    b->h_bricks = bg;
+  }
+  if (b->exec) {
+    const SceneG sc = make_scene(w);
+    if (memcmp(&sc, &b->cap_scene, sizeof(SceneG)) != 0 || b->cap_tf != w->tf_dev) {
+      DPR_HIP(hipStreamSynchronize(w->dev->stream));
+      b->drop_graph();
+    }
+  }
   return DPR_OK;
 }
 
 static bool same_key(const BatchState* b, dpr_world w, const dpr_camera* cams, int n, const dpr_frame* outs, int tw,
                      int th) {
   if (!b || b->tile_w != tw || b->tile_h != th || (int)b->cams.size() != n) return false;
-  if (b->version != w->version) return false;
+  if (b->geo_version != w->geo_version || b->skip != !(w->params.flags & DPR_FLAG_NO_SKIP)) return false;
   if (memcmp(b->cams.data(), cams, n * sizeof(dpr_camera)) != 0) return false;
   for (int c = 0; c < n; ++c)
     if (b->outs[c] != outs[c] || b->out_ptrs[2 * c] != outs[c]->rgba || b->out_ptrs[2 * c + 1] != outs[c]->depth)
@@ -516,6 +553,9 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
   if (s != DPR_OK) return s;
   if (!same_key(b, w, cams, n, outs, tw, th)) {
     s = build_batch(w, b, cams, n, outs, tw, th);
+    if (s != DPR_OK) return s;
+  } else {
+    s = refresh_batch(w, b);
     if (s != DPR_OK) return s;
   }
   if (flags & DPR_FLAG_NO_GRAPH) {

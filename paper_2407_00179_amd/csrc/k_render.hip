@@ -46,19 +46,30 @@ __global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src
 
 // ------------------------------------------------------------------ macrocell ranges
 // Macrocell m covers owned-relative voxels [mc m - 1, mc m + mc] per axis, clipped to
-// the stored range (stored index = owned index + ghost_lo).  One workgroup builds a
-// run of up to (kMaxRow - 2) / mc macrocells along x for one (my, mz): its 4 waves
-// split the (y, z) rows of the window, each wave reads the rows' x-span from the
-// linear stored copy (coalesced) and keeps a per-x-column min/max in registers; the
+// the stored range (stored index = owned index + ghost_lo).  One workgroup of 8
+// waves builds a run of up to (64 P - 2) / mc macrocells along x for one (my, mz):
+// the waves split the (y, z) rows of the window, each reads its rows' x-span from
+// the linear stored copy (coalesced, U rows in flight at once, addresses clamped
+// into the window so every load is unconditional) and keeps a per-x-column
+// min/max in registers (P columns per lane, P sized to the brick's width); the
 // columns are combined in LDS and reduced over each macrocell's x-window.  Each
 // element is read at most ((mc+2)/mc)^2 times in total (the y and z aprons).
-constexpr int kMaxRow = 2112;
+constexpr int kMcWaves = 8;
 
 template <typename T>
-__global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vox, int sx, int sy, int sz, int gx,
-                                                        int gy, int gz, int mc, int mdx, int mdy, int mdz,
-                                                        int per_chunk, int chunks, float2* __restrict__ ranges) {
-  __shared__ float col_lo[kMaxRow], col_hi[kMaxRow];
+__device__ __forceinline__ float voxel_value(const T* p) {
+  if constexpr (sizeof(T) == 2)
+    return __half2float(*p);
+  else
+    return *p;
+}
+
+template <typename T, int P, int U>
+__global__ __launch_bounds__(64 * kMcWaves) void macrocell_kernel(const T* __restrict__ vox, int sx, int sy, int sz,
+                                                                  int gx, int gy, int gz, int mc, int mdx, int mdy,
+                                                                  int mdz, int per_chunk, int chunks,
+                                                                  float2* __restrict__ ranges) {
+  __shared__ float col_lo[64 * P], col_hi[64 * P];
   const int c = blockIdx.x % chunks;
   const int my = (blockIdx.x / chunks) % mdy, mz = blockIdx.x / (chunks * mdy);
   const int mx0 = c * per_chunk, mx1 = min(mdx, mx0 + per_chunk);
@@ -67,38 +78,40 @@ __global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vo
   const int y0 = max(0, mc * my - 1 + gy), y1 = min(sy - 1, mc * my + mc + gy);
   const int z0 = max(0, mc * mz - 1 + gz), z1 = min(sz - 1, mc * mz + mc + gz);
   const int wy = y1 - y0 + 1, rows = wy * (z1 - z0 + 1);
-  for (int x = threadIdx.x; x < wx; x += 256) {
+  for (int x = threadIdx.x; x < wx; x += 64 * kMcWaves) {
     col_lo[x] = INFINITY;
     col_hi[x] = -INFINITY;
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int P = (kMaxRow + 63) / 64;  // x positions per lane
   float lo[P], hi[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     lo[j] = INFINITY;
     hi[j] = -INFINITY;
   }
-  for (int r = wave; r < rows; r += 4) {
-    const int y = y0 + r % wy, z = z0 + r / wy;
-    const T* rowp = vox + ((size_t)z * sy + y) * sx + xs;
+  for (int r0 = wave; r0 < rows; r0 += kMcWaves * U) {
+    float v[U][P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int x = lane + 64 * j;
-      if (x < wx) {
-        float v;
-        if constexpr (sizeof(T) == 2)
-          v = __half2float(rowp[x]);
-        else
-          v = rowp[x];
-        lo[j] = fminf(lo[j], v);
-        hi[j] = fmaxf(hi[j], v);
+    for (int u = 0; u < U; ++u) {
+      const int r = min(r0 + u * kMcWaves, rows - 1);
+      const T* rowp = vox + ((size_t)(z0 + r / wy) * sy + (y0 + r % wy)) * sx + xs;
+#pragma unroll
+      for (int j = 0; j < P; ++j) v[u][j] = voxel_value(rowp + min(lane + 64 * j, wx - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool row_ok = r0 + u * kMcWaves < rows;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const bool ok = row_ok && lane + 64 * j < wx;
+        lo[j] = ok ? fminf(lo[j], v[u][j]) : lo[j];
+        hi[j] = ok ? fmaxf(hi[j], v[u][j]) : hi[j];
       }
     }
   }
-  // combine the 4 waves' columns in LDS, one wave at a time
-  for (int w = 0; w < 4; ++w) {
+  // combine the waves' columns in LDS, one wave at a time
+  for (int w = 0; w < kMcWaves; ++w) {
     if (wave == w) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(256) void macrocell_kernel(const T* __restrict__ vo
     __syncthreads();
   }
   // reduce each macrocell's x-window [mc mx - 1, mc mx + mc] (stored coordinates)
-  for (int mx = mx0 + threadIdx.x; mx < mx1; mx += 256) {
+  for (int mx = mx0 + threadIdx.x; mx < mx1; mx += 64 * kMcWaves) {
     const int a0 = max(0, mc * mx - 1 + gx) - xs, a1 = min(sx - 1, mc * mx + mc + gx) - xs;
     float a = INFINITY, b = -INFINITY;
     for (int x = a0; x <= a1; ++x) {
@@ -199,19 +212,38 @@ hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, i
   return hipGetLastError();
 }
 
-hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st) {
-  int gx = b.olo[0] - b.slo[0], gy = b.olo[1] - b.slo[1], gz = b.olo[2] - b.slo[2];
-  const int per_chunk = (kMaxRow - 2) / mc;
+template <typename T, int P, int U>
+static void launch_mc(const void* linear, const BrickG& b, int mc, float2* ranges, hipStream_t st) {
+  const int gx = b.olo[0] - b.slo[0], gy = b.olo[1] - b.slo[1], gz = b.olo[2] - b.slo[2];
+  const int per_chunk = (64 * P - 2) / mc;
   const int chunks = (b.mdim[0] + per_chunk - 1) / per_chunk;
   dim3 grid(chunks * b.mdim[1] * b.mdim[2]);
-  if (f16)
-    hipLaunchKernelGGL(macrocell_kernel<__half>, grid, dim3(256), 0, st, (const __half*)linear, b.sdim[0],
-                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], per_chunk, chunks,
-                       ranges);
+  hipLaunchKernelGGL((macrocell_kernel<T, P, U>), grid, dim3(64 * kMcWaves), 0, st, (const T*)linear, b.sdim[0],
+                     b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], per_chunk, chunks,
+                     ranges);
+}
+
+template <typename T>
+static void launch_mc_t(const void* linear, const BrickG& b, int mc, float2* ranges, hipStream_t st) {
+  // columns per lane: the narrowest instantiation that spans the brick's x-window
+  const int need = std::min(b.sdim[0], mc * b.mdim[0] + 2);
+  if (need <= 64 * 2)
+    launch_mc<T, 2, 4>(linear, b, mc, ranges, st);
+  else if (need <= 64 * 3)
+    launch_mc<T, 3, 4>(linear, b, mc, ranges, st);
+  else if (need <= 64 * 5)
+    launch_mc<T, 5, 4>(linear, b, mc, ranges, st);
+  else if (need <= 64 * 9)
+    launch_mc<T, 9, 2>(linear, b, mc, ranges, st);
   else
-    hipLaunchKernelGGL(macrocell_kernel<float>, grid, dim3(256), 0, st, (const float*)linear, b.sdim[0],
-                       b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], per_chunk, chunks,
-                       ranges);
+    launch_mc<T, 17, 1>(linear, b, mc, ranges, st);  // wider bricks: runs of x-chunks
+}
+
+hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st) {
+  if (f16)
+    launch_mc_t<__half>(linear, b, mc, ranges, st);
+  else
+    launch_mc_t<float>(linear, b, mc, ranges, st);
   return hipGetLastError();
 }
 

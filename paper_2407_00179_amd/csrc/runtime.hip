@@ -355,6 +355,8 @@ void dpr_world_release(dpr_world w) {
   for (auto f : w->partials) dpr_frame_release(f);
   if (w->batch) batch_state_free(w->batch);
   dev_free(w->tf_dev);
+  if (w->tf_host) (void)hipHostFree(w->tf_host);
+  if (w->tf_ev) (void)hipEventDestroy(w->tf_ev);
   delete w;
 }
 
@@ -400,6 +402,7 @@ dpr_status dpr_world_add_brick(dpr_world w, const void* voxels, dpr_dtype dtype,
   }
   w->bricks.push_back(b);
   w->committed = false;
+  ++w->geo_version;
   *brick_id = (int32_t)w->bricks.size() - 1;
   return DPR_OK;
 }
@@ -498,9 +501,9 @@ dpr_status dpr_world_commit(dpr_world w) {
     BrickG g = b.device_view(false);
     DPR_HIP(launch_macrocells(b.linear, g, b.dtype == DPR_F16, mc, b.ranges, w->dev->stream));
   }
-  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  // (stream-ordered: later renders on the device stream see the new data; the
+  // host does not wait)
   w->committed = true;
-  ++w->version;
   return DPR_OK;
 }
 
@@ -550,14 +553,23 @@ dpr_status dpr_set_transfer_function(dpr_world w, const float* rgba, int32_t n, 
     if (st != DPR_OK) return st;
     w->ntf = n;
   }
-  DPR_HIP(hipMemcpyAsync(w->tf_dev, rgba, (size_t)n * sizeof(float4), hipMemcpyHostToDevice, w->dev->stream));
-  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  // stage through pinned host memory so the upload is stream-ordered and the host
+  // does not wait for the device; the staging buffer is reused once the previous
+  // upload has been consumed
+  if (!w->tf_host) {
+    DPR_HIP(hipHostMalloc((void**)&w->tf_host, kMaxTF * sizeof(float4), hipHostMallocDefault));
+    DPR_HIP(hipEventCreateWithFlags(&w->tf_ev, hipEventDisableTiming));
+  }
+  if (w->tf_ev_pending) DPR_HIP(hipEventSynchronize(w->tf_ev));
+  memcpy(w->tf_host, rgba, (size_t)n * sizeof(float4));
+  DPR_HIP(hipMemcpyAsync(w->tf_dev, w->tf_host, (size_t)n * sizeof(float4), hipMemcpyHostToDevice, w->dev->stream));
+  DPR_HIP(hipEventRecord(w->tf_ev, w->dev->stream));
+  w->tf_ev_pending = true;
   w->tf_lo = lo;
   w->tf_hi = hi;
   w->density = density;
   w->tf_set = true;
   ++w->tf_version;
-  ++w->version;
   return DPR_OK;
 }
 
@@ -582,7 +594,6 @@ dpr_status dpr_set_render_params(dpr_world w, const dpr_render_params* p) {
                 mc);
   if (mc != w->params.macrocell_cells) w->committed = false;
   w->params = *p;
-  ++w->version;
   return DPR_OK;
 }
 

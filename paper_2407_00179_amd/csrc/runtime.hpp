@@ -107,7 +107,11 @@ struct dpr_world_t {
   // partial frames of dpr_render_frame (one per brick)
   std::vector<dpr_frame> partials;
   dpr::BatchState* batch = nullptr;
-  uint64_t version = 1;  // bumped by commit, TF and parameter changes (invalidates batch graphs)
+  uint64_t geo_version = 1;  // bumped when a brick is added (invalidates batch item lists)
+  // pinned staging for transfer-function uploads; tf_ev marks the last upload
+  float4* tf_host = nullptr;
+  hipEvent_t tf_ev = nullptr;
+  bool tf_ev_pending = false;
   int batch_tile_w = 8, batch_tile_h = 8;
 };
 

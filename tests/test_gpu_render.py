@@ -156,6 +156,27 @@ def test_macrocells_and_majorants_bitwise(gpu_lib, dpr):
         w.release()
 
 
+@pytest.mark.parametrize("dims,dtype", [((150, 9, 7), np.float32), ((300, 8, 6), np.float16),
+                                        ((520, 6, 5), np.float32), ((1100, 5, 4), np.float32)])
+def test_macrocells_wide_bricks(gpu_lib, dpr, dims, dtype):
+    """Brick widths that take each column count of the range builder, and x-chunked runs."""
+    vol = make_volume_small(dims, make_blobs(dims, 5, 4, (0.1, 0.3)), 6, 0.05, dtype)
+    tf = make_tf(2001)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 8, 8)
+    h = dims[0] // 2 + 3
+    for boxes in ([((0, 0, 0), dims)], [((0, 0, 0), (h, dims[1], dims[2])), ((h, 0, 0), dims)]):
+        for mc in (2, 16):
+            w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=mc)
+            for i, (lo, hi) in enumerate(boxes):
+                b = extract_brick(vol, dims, lo, hi)
+                want_r = oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, mc)
+                got_r, got_m = w.macrocells(i)
+                assert np.array_equal(got_r, want_r), (dims, len(boxes), mc, i)
+                assert np.array_equal(got_m, oracle.majorants(want_r, tf)), (dims, len(boxes), mc, i)
+            w.release()
+
+
 def test_f16_volume(gpu_lib, dpr):
     dims = (50, 42, 36)
     vol, tf = _small_case(dims, seed=41, dtype=np.float16)
