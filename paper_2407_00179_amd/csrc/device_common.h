@@ -30,6 +30,7 @@ struct BrickG {
   const float* majorant;  // per macrocell, x fastest (may be null when skipping is off)
   int mdim[3];            // macrocell grid
   int mc_shift;           // log2(macrocell edge)
+  int wide;               // blocked array of 4 GiB or more (64-bit voxel offsets)
 };
 
 // Scene-wide render constants.
@@ -43,6 +44,32 @@ struct SceneG {
 __device__ __forceinline__ uint32_t blk_x(int i) { return ((uint32_t)(i >> 3) << 9) + (uint32_t)(i & 7); }
 __device__ __forceinline__ uint32_t blk_y(int j, uint32_t bsy) { return (uint32_t)(j >> 3) * bsy + (uint32_t)((j & 7) << 3); }
 __device__ __forceinline__ uint32_t blk_z(int k, uint32_t bsz) { return (uint32_t)(k >> 3) * bsz + (uint32_t)((k & 7) << 6); }
+
+// Byte offsets of the same layout for elements of 1 << SH bytes (bsy_b, bsz_b:
+// byte strides), for bricks whose blocked array is below 4 GiB: a voxel is then
+// one global load from the brick's base (a scalar register pair) plus a 32-bit
+// vector offset, with no per-lane 64-bit address arithmetic.
+template <int SH>
+__device__ __forceinline__ uint32_t blkb_x(int i) {
+  return ((uint32_t)(i >> 3) << (9 + SH)) + ((uint32_t)(i & 7) << SH);
+}
+template <int SH>
+__device__ __forceinline__ uint32_t blkb_y(int j, uint32_t bsy_b) {
+  return (uint32_t)(j >> 3) * bsy_b + ((uint32_t)(j & 7) << (3 + SH));
+}
+template <int SH>
+__device__ __forceinline__ uint32_t blkb_z(int k, uint32_t bsz_b) {
+  return (uint32_t)(k >> 3) * bsz_b + ((uint32_t)(k & 7) << (6 + SH));
+}
+template <typename T>
+__device__ __forceinline__ float load_voxel_b(const void* base, uint32_t boff) {
+  using GC = const char __attribute__((address_space(1)))*;
+  const GC q = (GC)base + boff;
+  if constexpr (sizeof(T) == 2)
+    return __half2float(__ushort_as_half(*(const unsigned short __attribute__((address_space(1)))*)q));
+  else
+    return *(const float __attribute__((address_space(1)))*)q;
+}
 
 template <typename T> __device__ __forceinline__ float load_voxel(const T* p, uint32_t off);
 template <> __device__ __forceinline__ float load_voxel<float>(const float* p, uint32_t off) { return p[off]; }

@@ -40,7 +40,7 @@ constexpr int kChunk = 8;  // segments between refill checks
 
 __global__ void reset_head_kernel(int* head) { *head = 0; }
 
-template <typename T, bool SKIP>
+template <typename T, bool SKIP, bool WIDE>
 __global__ __launch_bounds__(256) void batch_march_kernel(SceneG sc, BatchG bg, const float4* __restrict__ tf) {
   extern __shared__ float4 tf_lds[];
   float4* tfb = tf_lds;
@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void batch_march_kernel(SceneG sc, BatchG bg, 
         if (pending >= 0 || exhausted) break;
         int it = 0;
         if (lane == 0) it = atomicAdd(bg.head, 1);
-        it = __shfl(it, 0);
+        // wave-uniform: the item, and so the brick, live in scalar registers
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
         if (it >= bg.n_items) {
           exhausted = true;
           break;
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void batch_march_kernel(SceneG sc, BatchG bg, 
     }
     // ---- march a chunk of segments
     if (active) {
-      if (ray_advance<T, SKIP>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk)) {
+      if (ray_advance<T, SKIP, WIDE>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk)) {
         bg.frag_rgba[slot] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
         bg.frag_depth[slot] = (float)r.t_in;
         active = false;
@@ -228,6 +229,11 @@ struct BatchState {
     head = nullptr;
     drop_graph();
   }
+  bool wide() const {
+    for (const auto& g : h_bricks)
+      if (g.wide) return true;
+    return false;
+  }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -284,6 +290,16 @@ static dpr_status upload(V** dst, const std::vector<V>& src, hipStream_t st, con
   return DPR_OK;
 }
 
+template <typename T, bool SKIP>
+static const void* march_fn_t(bool wide) {
+  return wide ? (const void*)batch_march_kernel<T, SKIP, true> : (const void*)batch_march_kernel<T, SKIP, false>;
+}
+
+static const void* march_fn(bool f16, bool skip, bool wide) {
+  if (f16) return skip ? march_fn_t<__half, true>(wide) : march_fn_t<__half, false>(wide);
+  return skip ? march_fn_t<float, true>(wide) : march_fn_t<float, false>(wide);
+}
+
 static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool timed) {
   SceneG sc = make_scene(w);
   BatchG g{};
@@ -300,17 +316,10 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, b->head);
   if (timed) (void)hipEventRecord(b->ev[0], st);
-  if (f16) {
-    if (b->skip)
-      hipLaunchKernelGGL((batch_march_kernel<__half, true>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
-    else
-      hipLaunchKernelGGL((batch_march_kernel<__half, false>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
-  } else {
-    if (b->skip)
-      hipLaunchKernelGGL((batch_march_kernel<float, true>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
-    else
-      hipLaunchKernelGGL((batch_march_kernel<float, false>), dim3(b->grid), dim3(256), lds, st, sc, g, w->tf_dev);
-  }
+  const void* fn = march_fn(f16, b->skip, b->wide());
+  void* args[] = {(void*)&sc, (void*)&g, (void*)&w->tf_dev};
+  const hipError_t le = hipLaunchKernel(fn, dim3(b->grid), dim3(256), args, lds, st);
+  if (le != hipSuccess) return le;
   if (timed) (void)hipEventRecord(b->ev[1], st);
   const int tp = b->tile_w * b->tile_h;
   const int chunks = (tp + 63) / 64;
@@ -422,12 +431,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   const bool f16 = w->bricks[0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipError_t e;
-  if (f16)
-    e = b->skip ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_march_kernel<__half, true>, 256, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_march_kernel<__half, false>, 256, lds);
-  else
-    e = b->skip ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_march_kernel<float, true>, 256, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_march_kernel<float, false>, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, march_fn(f16, b->skip, b->wide()), 256, lds);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   b->grid = w->dev->cu_count * per_cu;
   return DPR_OK;

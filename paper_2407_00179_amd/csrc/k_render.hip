@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void majorant_kernel(const float2* __restrict_
 // Plain per-brick launch: one thread per pixel, 16x16 tiles as four 8x8 waves,
 // tiles assigned so that each XCD (round-robin workgroup dispatch) walks one
 // contiguous band of the screen and keeps its part of the brick in its own L2.
-template <typename T, bool SKIP>
+template <typename T, bool SKIP, bool WIDE>
 __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG cam, const float4* __restrict__ tf,
                                                     float4* __restrict__ out_rgba, float* __restrict__ out_depth,
                                                     int* __restrict__ out_count, int tiles_x, int n_tiles) {
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
   RayState r;
   const size_t p = (size_t)py * cam.W + px;
   if (ray_begin(sc, b, cam.eye, d, r)) {
-    ray_advance<T, SKIP>(sc, b, tfb, tfs, r, 0x7fffffff);
+    ray_advance<T, SKIP, WIDE>(sc, b, tfb, tfs, r, 0x7fffffff);
     out_rgba[p] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
     out_depth[p] = (float)r.t_in;
   } else {
@@ -261,20 +261,19 @@ hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, cons
   int nb = ((n_tiles + 7) / 8) * 8;
   dim3 grid(nb), block(256);
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, sc, b, cam, tf, rgba, depth, count, tx, n_tiles);
+  };
   if (f16) {
     if (skip)
-      hipLaunchKernelGGL((march_kernel<__half, true>), grid, block, lds, st, sc, b, cam, tf, rgba, depth, count, tx,
-                         n_tiles);
+      b.wide ? go(march_kernel<__half, true, true>) : go(march_kernel<__half, true, false>);
     else
-      hipLaunchKernelGGL((march_kernel<__half, false>), grid, block, lds, st, sc, b, cam, tf, rgba, depth, count, tx,
-                         n_tiles);
+      b.wide ? go(march_kernel<__half, false, true>) : go(march_kernel<__half, false, false>);
   } else {
     if (skip)
-      hipLaunchKernelGGL((march_kernel<float, true>), grid, block, lds, st, sc, b, cam, tf, rgba, depth, count, tx,
-                         n_tiles);
+      b.wide ? go(march_kernel<float, true, true>) : go(march_kernel<float, true, false>);
     else
-      hipLaunchKernelGGL((march_kernel<float, false>), grid, block, lds, st, sc, b, cam, tf, rgba, depth, count, tx,
-                         n_tiles);
+      b.wide ? go(march_kernel<float, false, true>) : go(march_kernel<float, false, false>);
   }
   return hipGetLastError();
 }

@@ -7,7 +7,8 @@
 // one macrocell; the run length is computed exactly in integers, a run in a
 // macrocell of majorant 0 is skipped in O(1), and the other runs sample every
 // segment with no per-sample macrocell logic.  Voxel gathers of the next sample
-// are issued before the current sample is shaded.
+// are issued before the current sample is shaded.  For bricks below 4 GiB a voxel
+// address is a 32-bit byte offset from the brick base.
 #pragma once
 
 #include "device_common.h"
@@ -109,24 +110,44 @@ struct Gather {
   float fx, fy, fz;
 };
 
-template <typename T>
-__device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const T* vox, const int64_t p[3],
-                                       Gather<T>& g) {
+// Gather the 8 voxels around a sample point.  WIDE: the brick's blocked array is
+// 4 GiB or more, so offsets are formed in 64 bits; otherwise as 32-bit byte
+// offsets from the brick base.
+template <typename T, bool WIDE>
+__device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const int64_t p[3], Gather<T>& g) {
   int lx, ly, lz;
   clamp_axis(p[0], sc.dims[0], b.slo[0], b.sdim[0], lx, g.fx);
   clamp_axis(p[1], sc.dims[1], b.slo[1], b.sdim[1], ly, g.fy);
   clamp_axis(p[2], sc.dims[2], b.slo[2], b.sdim[2], lz, g.fz);
-  const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
-  const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
-  const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
-  g.v[0] = load_voxel<T>(vox, x0 + y0 + z0);
-  g.v[1] = load_voxel<T>(vox, x1 + y0 + z0);
-  g.v[2] = load_voxel<T>(vox, x0 + y1 + z0);
-  g.v[3] = load_voxel<T>(vox, x1 + y1 + z0);
-  g.v[4] = load_voxel<T>(vox, x0 + y0 + z1);
-  g.v[5] = load_voxel<T>(vox, x1 + y0 + z1);
-  g.v[6] = load_voxel<T>(vox, x0 + y1 + z1);
-  g.v[7] = load_voxel<T>(vox, x1 + y1 + z1);
+  if constexpr (WIDE) {
+    const T* vox = (const T*)b.data;
+    const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
+    const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
+    const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
+    g.v[0] = load_voxel<T>(vox, x0 + y0 + z0);
+    g.v[1] = load_voxel<T>(vox, x1 + y0 + z0);
+    g.v[2] = load_voxel<T>(vox, x0 + y1 + z0);
+    g.v[3] = load_voxel<T>(vox, x1 + y1 + z0);
+    g.v[4] = load_voxel<T>(vox, x0 + y0 + z1);
+    g.v[5] = load_voxel<T>(vox, x1 + y0 + z1);
+    g.v[6] = load_voxel<T>(vox, x0 + y1 + z1);
+    g.v[7] = load_voxel<T>(vox, x1 + y1 + z1);
+  } else {
+    constexpr int SH = sizeof(T) == 2 ? 1 : 2;
+    const uint32_t bsy = b.bsy << SH, bsz = b.bsz << SH;
+    const uint32_t x0 = blkb_x<SH>(lx), x1 = blkb_x<SH>(lx + 1);
+    const uint32_t y0 = blkb_y<SH>(ly, bsy), y1 = blkb_y<SH>(ly + 1, bsy);
+    const uint32_t z0 = blkb_z<SH>(lz, bsz), z1 = blkb_z<SH>(lz + 1, bsz);
+    const uint32_t a00 = x0 + y0, a10 = x1 + y0, a01 = x0 + y1, a11 = x1 + y1;
+    g.v[0] = load_voxel_b<T>(b.data, a00 + z0);
+    g.v[1] = load_voxel_b<T>(b.data, a10 + z0);
+    g.v[2] = load_voxel_b<T>(b.data, a01 + z0);
+    g.v[3] = load_voxel_b<T>(b.data, a11 + z0);
+    g.v[4] = load_voxel_b<T>(b.data, a00 + z1);
+    g.v[5] = load_voxel_b<T>(b.data, a10 + z1);
+    g.v[6] = load_voxel_b<T>(b.data, a01 + z1);
+    g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
+  }
 }
 
 // Shade one sample; returns true when the ray terminates early.
@@ -161,10 +182,9 @@ __device__ __forceinline__ bool shade(const SceneG& sc, const float4* __restrict
 // Advance by at most `budget` lattice segments.  Returns true once the ray is
 // finished: past its last segment, or terminated early (1 - T >= ert, tested
 // after every segment that changed T).
-template <typename T, bool SKIP>
+template <typename T, bool SKIP, bool WIDE>
 __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
                                             const float4* __restrict__ tfs, RayState& r, int budget) {
-  const T* vox = (const T*)b.data;
   const float Ddt = sc.density * sc.dt_f;
   int s = r.s;
   int n = r.n;
@@ -207,29 +227,47 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
       continue;
     }
     budget -= run;
-    Gather<T> cur;
-    {
-      const int64_t pc[3] = {p0, p1, p2};
-      gather<T>(sc, b, vox, pc, cur);
-    }
-    for (int i = 0; i < run; ++i) {
-      p0 += d0;
-      p1 += d1;
-      p2 += d2;
-      Gather<T> nxt;
-      const bool more = i + 1 < run;
-      if (more) {
-        const int64_t pn[3] = {p0, p1, p2};
-        gather<T>(sc, b, vox, pn, nxt);
-      }
+    // one sample per step, the next sample's voxels requested before this one is
+    // shaded; two steps per trip alternate the gather buffers (no register copies).
+    // The request is unconditional (past the run's last sample it reads clamped,
+    // in-brick voxels that are never used), so the wait before shading covers only
+    // the older request.
+    auto step = [&](const Gather<T>& g) -> bool {
       const float Dl = (s == r.s0) ? r.dl_first : ((s == r.s1) ? r.dl_last : Ddt);
       ++n;
       ++s;
-      if (shade<T>(sc, tfb, tfs, cur, Dl, tau_acc, tr, cr, cg, cb)) {
+      return shade<T>(sc, tfb, tfs, g, Dl, tau_acc, tr, cr, cg, cb);
+    };
+    Gather<T> ga, gb;
+    {
+      const int64_t pc[3] = {p0, p1, p2};
+      gather<T, WIDE>(sc, b, pc, ga);
+    }
+    for (int i = 0;;) {
+      p0 += d0;
+      p1 += d1;
+      p2 += d2;
+      {
+        const int64_t pn[3] = {p0, p1, p2};
+        gather<T, WIDE>(sc, b, pn, gb);
+      }
+      if (step(ga)) {
         done = true;
         break;
       }
-      if (more) cur = nxt;
+      if (++i >= run) break;
+      p0 += d0;
+      p1 += d1;
+      p2 += d2;
+      {
+        const int64_t pn[3] = {p0, p1, p2};
+        gather<T, WIDE>(sc, b, pn, ga);
+      }
+      if (step(gb)) {
+        done = true;
+        break;
+      }
+      if (++i >= run) break;
     }
   }
   // the fixed-point position always corresponds to segment s

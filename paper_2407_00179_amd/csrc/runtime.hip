@@ -140,6 +140,7 @@ BrickG Brick::device_view(bool with_majorant) const {
   g.bsy = (uint32_t)kBlockVoxels * (uint32_t)bdim[0];
   g.bsz = (uint32_t)kBlockVoxels * (uint32_t)bdim[0] * (uint32_t)bdim[1];
   g.majorant = with_majorant ? maj : nullptr;
+  g.wide = (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * elem() > 0xffffffffull;
   int sh = 0;
   while ((1 << sh) < mc) ++sh;
   g.mc_shift = sh;
