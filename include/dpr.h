@@ -62,6 +62,9 @@ typedef enum { DPR_F32 = 0, DPR_F16 = 1 } dpr_dtype;
 #define DPR_FLAG_NO_SKIP 0x1u    /* disable macrocell empty-space skipping          */
 #define DPR_FLAG_PLAIN 0x2u      /* one plain launch per (camera, brick) + composite  */
 #define DPR_FLAG_NO_GRAPH 0x4u   /* batched paths: enqueue directly, no graph replay */
+/* render parameter: form voxel offsets in 64 bits for every brick (automatic for
+ * bricks whose blocked array is 4 GiB or more); the results are identical       */
+#define DPR_FLAG_WIDE_OFFSETS 0x8u
 
 typedef struct dpr_device_t* dpr_device; /* one GPU + one HIP stream              */
 typedef struct dpr_world_t* dpr_world;   /* this rank's bricks + TF + camera      */
@@ -80,7 +83,8 @@ typedef struct {
 /* step_voxels: lattice step dt = step_voxels * h, in (0, 1].
  * ert_threshold: stop a ray once 1 - T >= threshold; >= 1 disables.
  * macrocell_cells: macrocell edge in cells (power of two in [2, 64]).
- * flags: DPR_FLAG_NO_SKIP, DPR_FLAG_PLAIN, DPR_FLAG_NO_GRAPH (dpr_render_frame). */
+ * flags: DPR_FLAG_NO_SKIP, DPR_FLAG_PLAIN, DPR_FLAG_NO_GRAPH (dpr_render_frame),
+ * DPR_FLAG_WIDE_OFFSETS. */
 typedef struct {
   float step_voxels;
   float ert_threshold;

@@ -14,7 +14,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _native as N
-from ._native import DprError, F16, F32, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, check, lib  # noqa: F401
+from ._native import (DprError, F16, F32, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, FLAG_WIDE_OFFSETS,  # noqa: F401
+                      check, lib)
 
 __all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_camera", "render_train",
            "DprRenderFn"]

@@ -22,7 +22,7 @@ OK = 0
 STATUS = {0: "DPR_OK", -1: "DPR_ERR_INVALID_ARGUMENT", -2: "DPR_ERR_INVALID_STATE", -3: "DPR_ERR_OUT_OF_MEMORY",
           -4: "DPR_ERR_DEVICE", -5: "DPR_ERR_UNSUPPORTED"}
 F32, F16 = 0, 1
-FLAG_NO_SKIP, FLAG_PLAIN, FLAG_NO_GRAPH = 0x1, 0x2, 0x4
+FLAG_NO_SKIP, FLAG_PLAIN, FLAG_NO_GRAPH, FLAG_WIDE_OFFSETS = 0x1, 0x2, 0x4, 0x8
 
 
 class DprError(RuntimeError):

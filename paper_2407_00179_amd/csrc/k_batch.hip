@@ -358,7 +358,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   std::vector<CamG> cg(n);
   for (int c = 0; c < n; ++c) cg[c] = make_cam(cams[c]);
   std::vector<BrickG> bg;
-  for (const auto& br : w->bricks) bg.push_back(br.device_view(b->skip));
+  for (const auto& br : w->bricks) bg.push_back(br.device_view(b->skip, w->params.flags & DPR_FLAG_WIDE_OFFSETS));
   // items ordered (camera, brick, tile row, tile column): consecutive pops share a brick
   std::vector<BatchItem> items;
   std::vector<int> tiles_x(n), tile_base(n + 1, 0);
@@ -462,7 +462,7 @@ static dpr_status capture_graph(dpr_world w, BatchState* b) {
 // captured graph is dropped when an argument baked into it changed.
 static dpr_status refresh_batch(dpr_world w, BatchState* b) {
   std::vector<BrickG> bg;
-  for (const auto& br : w->bricks) bg.push_back(br.device_view(b->skip));
+  for (const auto& br : w->bricks) bg.push_back(br.device_view(b->skip, w->params.flags & DPR_FLAG_WIDE_OFFSETS));
   if (bg.size() != b->h_bricks.size() || memcmp(bg.data(), b->h_bricks.data(), bg.size() * sizeof(BrickG)) != 0) {
     hipStream_t st = w->dev->stream;
     DPR_HIP(hipStreamSynchronize(st));
@@ -540,7 +540,7 @@ static dpr_status render_plain(dpr_world w, const dpr_camera* cams, int n, dpr_f
     CamG cg = make_cam(cams[c]);
     for (int i = 0; i < K; ++i) {
       const Brick& br = w->bricks[i];
-      DPR_HIP(launch_march(sc, br.device_view(skip), cg, w->tf_dev, br.dtype == DPR_F16, skip,
+      DPR_HIP(launch_march(sc, br.device_view(skip, w->params.flags & DPR_FLAG_WIDE_OFFSETS), cg, w->tf_dev, br.dtype == DPR_F16, skip,
                            (float4*)b->plain_parts[i]->rgba, b->plain_parts[i]->depth, nullptr, w->dev->stream));
     }
     dpr_status s = composite_frames(w->dev, b->plain_parts.data(), ids.data(), K, outs[c]);

@@ -127,7 +127,7 @@ SceneG make_scene(const dpr_world_t* w) {
   return s;
 }
 
-BrickG Brick::device_view(bool with_majorant) const {
+BrickG Brick::device_view(bool with_majorant, bool force_wide) const {
   BrickG g{};
   g.data = blocked;
   for (int a = 0; a < 3; ++a) {
@@ -140,7 +140,7 @@ BrickG Brick::device_view(bool with_majorant) const {
   g.bsy = (uint32_t)kBlockVoxels * (uint32_t)bdim[0];
   g.bsz = (uint32_t)kBlockVoxels * (uint32_t)bdim[0] * (uint32_t)bdim[1];
   g.majorant = with_majorant ? maj : nullptr;
-  g.wide = (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * elem() > 0xffffffffull;
+  g.wide = force_wide || (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * elem() > 0xffffffffull;
   int sh = 0;
   while ((1 << sh) < mc) ++sh;
   g.mc_shift = sh;
@@ -689,7 +689,8 @@ static dpr_status render_brick(dpr_world w, int id, dpr_frame out) {
   const bool skip = !(w->params.flags & DPR_FLAG_NO_SKIP);
   SceneG sc = make_scene(w);
   CamG cam = make_cam(w->cam);
-  DPR_HIP(launch_march(sc, b.device_view(skip), cam, w->tf_dev, b.dtype == DPR_F16, skip, (float4*)out->rgba,
+  const BrickG g = b.device_view(skip, w->params.flags & DPR_FLAG_WIDE_OFFSETS);
+  DPR_HIP(launch_march(sc, g, cam, w->tf_dev, b.dtype == DPR_F16, skip, (float4*)out->rgba,
                        out->depth, out->counts, w->dev->stream));
   return DPR_OK;
 }

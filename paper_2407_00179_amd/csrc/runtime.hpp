@@ -81,7 +81,7 @@ struct Brick {
   int mc = 0;
   uint64_t maj_tf_version = 0;
   size_t elem() const { return dtype == DPR_F16 ? 2 : 4; }
-  BrickG device_view(bool with_majorant) const;
+  BrickG device_view(bool with_majorant, bool force_wide = false) const;
 };
 
 struct BatchState;  // persistent batched renderer (k_batch.hip)
