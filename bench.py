@@ -38,7 +38,34 @@ from synth import (even_split, extract_brick, get_config, make_blobs, make_tf,  
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # CUs x lanes x clock: lane-op slots per second (non-packed)
-OPS_PER_SAMPLE = 60              # algorithmic VALU lane-op slots per logical sample
+# Algorithmic VALU lane-op slots per logical sample: 8 gathers' addressing, ~14 for
+# the trilinear lerps, TF lookup + lerp, one exp, the accumulate FMAs, the advance
+# and the termination compares.
+OPS_PER_SAMPLE = 60
+
+# Counters of one batch_march_kernel launch on the default workload, valid only for
+# the kernel sources they were taken on (SHA-256 over march.h, k_batch.hip and
+# device_common.h, in that order); after any change the bench reports null for them
+# until they are measured again:
+#   traffic: HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB; factors
+#     from a plain 256 MiB device-to-device copy in the same runs);
+#   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
+MARCH_COUNTERS = {
+    "sources_sha256": "25f871008ca97ac479326e1e0f608d548f943c03e172168f14cbb4933b69e31a",
+    "traffic_bytes_per_launch": 334707461,
+    "fetch_kib": 156232, "write_kib": 14447, "fetch_scale": 1.9997, "write_scale": 1.0,
+    "valu_lane_instr_per_sample": 162.9,
+}
+
+
+def march_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2407_00179_amd", "csrc")
+    for f in ("march.h", "k_batch.hip", "device_common.h"):
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -355,6 +382,11 @@ def main():
     dev, r = bench_main(args, dpr, torch, bricks, dims, tf, cfg, cam)
     msamples = r["samples"] / (r["ms_per_step"] / 1e3) / 1e6
     achieved = OPS_PER_SAMPLE * r["samples"] / (r["march_ms"] / 1e3) / 1e12
+    counters_valid = march_sources_sha256() == MARCH_COUNTERS["sources_sha256"]
+    traffic = MARCH_COUNTERS["traffic_bytes_per_launch"] if counters_valid else None
+    # share of the VALU issue slots the launch used, from the measured instruction count
+    valu_issue_frac = (MARCH_COUNTERS["valu_lane_instr_per_sample"] * r["samples"] / (r["march_ms"] / 1e3)
+                       / 1e12 / VALU_PEAK_TOPS) if counters_valid else None
     line = {
         "metric": "Msamples/s (logical ray-march samples, render + composite)",
         "value": msamples,
@@ -373,9 +405,9 @@ def main():
                                "macrocell ranges), majorants, batched march of the 8 bricks, tile composite",
                    "logical_samples_per_step": r["samples"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                      "kernel": "batch_march_kernel", "ms_per_launch": r["march_ms"],
-                     "ops_per_sample": OPS_PER_SAMPLE},
+                     "ops_per_sample": OPS_PER_SAMPLE, "valu_issue_frac": valu_issue_frac},
         "phases_ms": {"batch_march": r["march_ms"], "tile_composite": r["tile_comp_ms"]},
         "batch_tile": r["tile"],
         "plain_per_brick": {"ms_render_and_composite": r["ms_plain"], "ms_8_marches": r["ms_plain_march"],
