@@ -251,6 +251,27 @@ struct BatchState {
 
 void batch_state_free(BatchState* s) { delete s; }
 
+// Length of the chord that the ray through pixel (x, y) cuts from the box [lo, hi]
+// (0 on a miss): the work estimate used to order a brick's tiles.
+static double chord_length(const CamG& c, double x, double y, const double lo[3], const double hi[3]) {
+  const double sx = (2.0 * (x + 0.5) / c.W - 1.0) * c.sx, sy = (1.0 - 2.0 * (y + 0.5) / c.H) * c.sy;
+  double d[3];
+  for (int a = 0; a < 3; ++a) d[a] = c.f[a] + sx * c.r[a] + sy * c.u[a];
+  const double inv = 1.0 / std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double tn = 0.0, tf = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    const double da = d[a] * inv;
+    if (da == 0.0) {
+      if (c.eye[a] < lo[a] || c.eye[a] > hi[a]) return 0.0;
+      continue;
+    }
+    const double t0 = (lo[a] - c.eye[a]) / da, t1 = (hi[a] - c.eye[a]) / da;
+    tn = std::max(tn, std::min(t0, t1));
+    tf = std::min(tf, std::max(t0, t1));
+  }
+  return tf > tn ? tf - tn : 0.0;
+}
+
 // Conservative screen rectangle (pixel indices, inclusive) of a box's projection.
 static void brick_screen_rect(const CamG& c, const double lo[3], const double hi[3], int& x0, int& y0, int& x1,
                               int& y1) {
@@ -359,7 +380,10 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   for (int c = 0; c < n; ++c) cg[c] = make_cam(cams[c]);
   std::vector<BrickG> bg;
   for (const auto& br : w->bricks) bg.push_back(br.device_view(b->skip, w->params.flags & DPR_FLAG_WIDE_OFFSETS));
-  // items ordered (camera, brick, tile row, tile column): consecutive pops share a brick
+  // items grouped by (camera, brick), so consecutive pops share a brick; inside a
+  // group, tiles by decreasing chord of their centre ray through the brick, so the
+  // longest rays start first and the rays still marching when a group (or the
+  // whole queue) runs out are short ones
   std::vector<BatchItem> items;
   std::vector<int> tiles_x(n), tile_base(n + 1, 0);
   for (int c = 0; c < n; ++c) {
@@ -379,11 +403,19 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
       int x0, y0, x1, y1;
       brick_screen_rect(cg[c], lo, hi, x0, y0, x1, y1);
       if (x1 < x0 || y1 < y0) continue;
+      std::vector<std::pair<double, BatchItem>> grp;
       for (int ty = y0 / th; ty <= y1 / th; ++ty)
-        for (int tx = x0 / tw; tx <= x1 / tw; ++tx) {
-          per_tile[tile_base[c] + ty * tiles_x[c] + tx].push_back((int)items.size());
-          items.push_back({c, k, tx, ty});
-        }
+        for (int tx = x0 / tw; tx <= x1 / tw; ++tx)
+          grp.push_back({chord_length(cg[c], tx * tw + 0.5 * (tw - 1), ty * th + 0.5 * (th - 1), lo, hi),
+                         BatchItem{c, k, tx, ty}});
+      std::stable_sort(grp.begin(), grp.end(),
+                       [](const std::pair<double, BatchItem>& a, const std::pair<double, BatchItem>& b2) {
+                         return a.first > b2.first;
+                       });
+      for (const auto& e : grp) {
+        per_tile[tile_base[c] + e.second.ty * tiles_x[c] + e.second.tx].push_back((int)items.size());
+        items.push_back(e.second);
+      }
     }
   }
   std::vector<int> tile_cam(tile_base[n]), tile_xy(2 * (size_t)tile_base[n]), tile_off(tile_base[n] + 1, 0),
