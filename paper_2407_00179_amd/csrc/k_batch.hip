@@ -36,7 +36,10 @@ struct BatchG {
   int* head;
 };
 
-constexpr int kChunk = 8;  // segments between refill checks
+// Segments between refill checks.  A return to the refill point costs a ballot,
+// the pool bookkeeping and a fresh exact macrocell-run computation, so checks are
+// kept rare; a lane that finishes early waits at most this many segments.
+constexpr int kChunk = 128;
 
 __global__ void reset_head_kernel(int* head) { *head = 0; }
 
