@@ -8,39 +8,34 @@ namespace dpr {
 
 // ------------------------------------------------------------------ relayout
 // Linear x-fastest stored brick -> 8^3 blocks (x fastest inside a block, blocks
-// x-fastest).  One workgroup re-tiles a row of 4 consecutive blocks (32 x 8 x 8
-// voxels): reads are whole 32-voxel rows, the tile is transposed through LDS and
-// written as one contiguous run of 4 blocks.  Padding voxels are zero and are
+// x-fastest).  Inside a block x is fastest, so the 8 voxels of one block row are
+// contiguous in both layouts and the re-tiling is a copy of aligned 4-voxel runs,
+// no transpose: a workgroup covers 64 x-voxels of 16 rows (y) of one z-slice, a
+// wave 4 consecutive rows, so its reads are 4 contiguous row segments and, per
+// block, its writes are the 4 rows' runs back to back (a whole 128-byte line in
+// FP32).  Padding voxels (beyond the stored dims) are zeroed at allocation and
 // never read by the sampler.
-template <typename E>
+template <typename E, typename V4>
 __global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src, E* __restrict__ dst, int sx,
-                                                       int sy, int sz, int bx, int by, int bz) {
-  __shared__ E tile[8][8][33];  // [z][y][x] with one pad column
-  const int groups_x = (bx + 3) >> 2;
-  const int g = blockIdx.x;
-  const int gx = g % groups_x;
-  const int rest = g / groups_x;
-  const int byi = rest % by, bzi = rest / by;
-  const int x0 = gx * 32, y0 = byi * 8, z0 = bzi * 8;
+                                                       int sy, uint32_t bsy, uint32_t bsz, int nxt, int nyt) {
   const int t = threadIdx.x;
-  const int lx = t & 31;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int row = (t >> 5) + 8 * i;  // 0..63 -> (y, z)
-    const int ly = row & 7, lz = row >> 3;
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    E v = E(0);
-    if (x < sx && y < sy && z < sz) v = src[((size_t)z * sy + y) * sx + x];
-    tile[lz][ly][lx] = v;
-  }
-  __syncthreads();
-  const int nblk = min(4, bx - gx * 4);
-  const size_t base = (((size_t)bzi * by + byi) * bx + (size_t)gx * 4) * kBlockVoxels;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int e = t + 256 * i;  // 0..2047: block-major, then z, y, x inside the block
-    const int blk = e >> 9, w = e & 511;
-    if (blk < nblk) dst[base + e] = tile[w >> 6][(w >> 3) & 7][blk * 8 + (w & 7)];
+  const int q = t & 15, yy = t >> 4;  // 16 four-voxel runs x 16 rows
+  const int bxi = blockIdx.x % nxt;
+  const int rest = blockIdx.x / nxt;
+  const int yb = rest % nyt, z = rest / nyt;
+  const int x0 = bxi * 64 + 4 * q, y = yb * 16 + yy;
+  if (x0 >= sx || y >= sy) return;
+  const E* s = src + ((size_t)z * sy + y) * sx + x0;
+  E* d = dst + ((size_t)blk_z(z, bsz) + blk_y(y, bsy) + blk_x(x0));
+  if (x0 + 4 <= sx) {
+    V4 v;
+    v.x = s[0];
+    v.y = s[1];
+    v.z = s[2];
+    v.w = s[3];
+    *(V4*)d = v;  // x0 is a multiple of 4: the run is aligned and inside one block row
+  } else {
+    for (int i = 0; i < sx - x0; ++i) d[i] = s[i];
   }
 }
 
@@ -202,13 +197,16 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
 // ------------------------------------------------------------------ host launchers
 hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
                            int bz, hipStream_t st) {
-  const int groups = ((bx + 3) / 4) * by * bz;
+  (void)bz;
+  const int nxt = (sx + 63) / 64, nyt = (sy + 15) / 16;
+  const uint32_t bsy = (uint32_t)kBlockVoxels * (uint32_t)bx, bsz = bsy * (uint32_t)by;
+  const dim3 grid((unsigned)nxt * nyt * sz);
   if (elem_bytes == 4)
-    hipLaunchKernelGGL(relayout_kernel<uint32_t>, dim3(groups), dim3(256), 0, st, (const uint32_t*)src,
-                       (uint32_t*)dst, sx, sy, sz, bx, by, bz);
+    hipLaunchKernelGGL((relayout_kernel<uint32_t, uint4>), grid, dim3(256), 0, st, (const uint32_t*)src,
+                       (uint32_t*)dst, sx, sy, bsy, bsz, nxt, nyt);
   else
-    hipLaunchKernelGGL(relayout_kernel<uint16_t>, dim3(groups), dim3(256), 0, st, (const uint16_t*)src,
-                       (uint16_t*)dst, sx, sy, sz, bx, by, bz);
+    hipLaunchKernelGGL((relayout_kernel<uint16_t, ushort4>), grid, dim3(256), 0, st, (const uint16_t*)src,
+                       (uint16_t*)dst, sx, sy, bsy, bsz, nxt, nyt);
   return hipGetLastError();
 }
 

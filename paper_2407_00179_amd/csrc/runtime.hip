@@ -480,6 +480,8 @@ dpr_status dpr_world_commit(dpr_world w) {
       size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.elem();
       st = dev_alloc(&b.blocked, bytes, "blocked brick");
       if (st != DPR_OK) return st;
+      // padding voxels (beyond the stored dims) are never written by the relayout
+      DPR_HIP(hipMemsetAsync(b.blocked, 0, bytes, w->dev->stream));
     }
     DPR_HIP(launch_relayout(b.linear, b.blocked, (int)b.elem(), b.sdim[0], b.sdim[1], b.sdim[2], b.bdim[0],
                             b.bdim[1], b.bdim[2], w->dev->stream));
