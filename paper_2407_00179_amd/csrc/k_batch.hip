@@ -40,6 +40,7 @@ struct BatchG {
 // the pool bookkeeping and a fresh exact macrocell-run computation, so checks are
 // kept rare; a lane that finishes early waits at most this many segments.
 constexpr int kChunk = 128;
+constexpr int kRefillLanes = 32;
 
 __global__ void reset_head_kernel(int* head) { *head = 0; }
 
@@ -134,7 +135,10 @@ __global__ __launch_bounds__(256) void batch_march_kernel(SceneG sc, BatchG bg, 
     }
     // ---- march a chunk of segments
     if (active) {
-      if (ray_advance<T, SKIP, WIDE>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk)) {
+      // early return for a refill (fewer than half the lanes marching), only while
+      // a refill can take rays
+      const int min_lanes = (!exhausted && pending < 0) ? kRefillLanes : 0;
+      if (ray_advance<T, SKIP, WIDE>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk, min_lanes)) {
         bg.frag_rgba[slot] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
         bg.frag_depth[slot] = (float)r.t_in;
         active = false;

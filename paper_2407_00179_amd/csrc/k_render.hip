@@ -1,5 +1,8 @@
 // Brick ingest (8^3 relayout), macrocell ranges, transfer-function majorants and
 // the per-brick emission-absorption ray march, for gfx950.
+#include <algorithm>
+#include <vector>
+
 #include "device_common.h"
 #include "kernels.h"
 #include "march.h"
@@ -59,14 +62,30 @@ __device__ __forceinline__ float voxel_value(const T* p) {
     return *p;
 }
 
+// Up to kMcJobs bricks of one element type and column count per launch; the
+// workgroups of job j follow those of job j - 1.
+struct McJob {
+  const void* vox;
+  float2* ranges;
+  int sx, sy, sz, gx, gy, gz, mdx, mdy, mdz, per_chunk, chunks, blocks;
+};
+constexpr int kMcJobs = 16;
+struct McJobs {
+  McJob job[kMcJobs];
+  int n;
+};
+
 template <typename T, int P, int U>
-__global__ __launch_bounds__(64 * kMcWaves) void macrocell_kernel(const T* __restrict__ vox, int sx, int sy, int sz,
-                                                                  int gx, int gy, int gz, int mc, int mdx, int mdy,
-                                                                  int mdz, int per_chunk, int chunks,
-                                                                  float2* __restrict__ ranges) {
+__global__ __launch_bounds__(64 * kMcWaves) void macrocell_kernel(McJobs jobs, int mc) {
   __shared__ float col_lo[64 * P], col_hi[64 * P];
-  const int c = blockIdx.x % chunks;
-  const int my = (blockIdx.x / chunks) % mdy, mz = blockIdx.x / (chunks * mdy);
+  int bid = blockIdx.x, j = 0;
+  while (j + 1 < jobs.n && bid >= jobs.job[j].blocks) bid -= jobs.job[j++].blocks;
+  const McJob& J = jobs.job[j];
+  const T* __restrict__ vox = (const T*)J.vox;
+  const int sx = J.sx, sy = J.sy, sz = J.sz, gx = J.gx, gy = J.gy, gz = J.gz;
+  const int mdx = J.mdx, mdy = J.mdy, chunks = J.chunks, per_chunk = J.per_chunk;
+  const int c = bid % chunks;
+  const int my = (bid / chunks) % mdy, mz = bid / (chunks * mdy);
   const int mx0 = c * per_chunk, mx1 = min(mdx, mx0 + per_chunk);
   const int xs = max(0, mc * mx0 - 1 + gx), xe = min(sx - 1, mc * mx1 + gx);
   const int wx = xe - xs + 1;
@@ -127,22 +146,25 @@ __global__ __launch_bounds__(64 * kMcWaves) void macrocell_kernel(const T* __res
       a = fminf(a, col_lo[x]);
       b = fmaxf(b, col_hi[x]);
     }
-    ranges[((size_t)mz * mdy + my) * mdx + mx] = make_float2(a, b);
+    J.ranges[((size_t)mz * mdy + my) * mdx + mx] = make_float2(a, b);
   }
 }
 
 // ------------------------------------------------------------------ majorants
 // Largest TF opacity over entries [floor(x_min) - 1, ceil(x_max) + 1] of the range's
 // table coordinates x = clamp((v - lo)/(hi - lo), 0, 1) (N - 1), taken in FP32.
-__global__ __launch_bounds__(256) void majorant_kernel(const float2* __restrict__ ranges, int count,
-                                                       const float4* __restrict__ tf, int ntf, float tf_lo,
-                                                       float tf_hi, float* __restrict__ maj) {
+// One launch for the macrocells of up to kMajJobs bricks: thread m of the
+// launch handles macrocell m of the concatenation of the jobs' grids.
+__global__ __launch_bounds__(256) void majorant_kernel(MajJobs jobs, const float4* __restrict__ tf, int ntf,
+                                                       float tf_lo, float tf_hi) {
   __shared__ float alpha[kMaxTF];
   for (int i = threadIdx.x; i < ntf; i += 256) alpha[i] = tf[i].w;
   __syncthreads();
   int m = blockIdx.x * 256 + threadIdx.x;
-  if (m >= count) return;
-  float2 r = ranges[m];
+  int j = 0;
+  while (j < jobs.n && m >= jobs.count[j]) m -= jobs.count[j++];
+  if (j >= jobs.n) return;
+  float2 r = jobs.ranges[j][m];
   float span = tf_hi - tf_lo;
   float ua = (r.x - tf_lo) / span;
   float ub = (r.y - tf_lo) / span;
@@ -154,7 +176,7 @@ __global__ __launch_bounds__(256) void majorant_kernel(const float2* __restrict_
   int e1 = min((int)ceilf(xb) + 1, ntf - 1);
   float a = 0.f;
   for (int e = e0; e <= e1; ++e) a = fmaxf(a, alpha[e]);
-  maj[m] = a;
+  jobs.maj[j][m] = a;
 }
 
 // Plain per-brick launch: one thread per pixel, 16x16 tiles as four 8x8 waves,
@@ -211,44 +233,69 @@ hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, i
 }
 
 template <typename T, int P, int U>
-static void launch_mc(const void* linear, const BrickG& b, int mc, float2* ranges, hipStream_t st) {
-  const int gx = b.olo[0] - b.slo[0], gy = b.olo[1] - b.slo[1], gz = b.olo[2] - b.slo[2];
-  const int per_chunk = (64 * P - 2) / mc;
-  const int chunks = (b.mdim[0] + per_chunk - 1) / per_chunk;
-  dim3 grid(chunks * b.mdim[1] * b.mdim[2]);
-  hipLaunchKernelGGL((macrocell_kernel<T, P, U>), grid, dim3(64 * kMcWaves), 0, st, (const T*)linear, b.sdim[0],
-                     b.sdim[1], b.sdim[2], gx, gy, gz, mc, b.mdim[0], b.mdim[1], b.mdim[2], per_chunk, chunks,
-                     ranges);
+static void launch_mc(const McBrick* bricks, const int* idx, int n, int mc, hipStream_t st) {
+  for (int i0 = 0; i0 < n; i0 += kMcJobs) {
+    McJobs jobs{};
+    long long total = 0;
+    for (int i = i0; i < std::min(n, i0 + kMcJobs); ++i) {
+      const BrickG& b = bricks[idx[i]].view;
+      McJob& J = jobs.job[jobs.n++];
+      J.vox = bricks[idx[i]].linear;
+      J.ranges = bricks[idx[i]].ranges;
+      J.sx = b.sdim[0];
+      J.sy = b.sdim[1];
+      J.sz = b.sdim[2];
+      J.gx = b.olo[0] - b.slo[0];
+      J.gy = b.olo[1] - b.slo[1];
+      J.gz = b.olo[2] - b.slo[2];
+      J.mdx = b.mdim[0];
+      J.mdy = b.mdim[1];
+      J.mdz = b.mdim[2];
+      J.per_chunk = (64 * P - 2) / mc;
+      J.chunks = (b.mdim[0] + J.per_chunk - 1) / J.per_chunk;
+      J.blocks = J.chunks * b.mdim[1] * b.mdim[2];
+      total += J.blocks;
+    }
+    hipLaunchKernelGGL((macrocell_kernel<T, P, U>), dim3((unsigned)total), dim3(64 * kMcWaves), 0, st, jobs, mc);
+  }
+}
+
+// Columns per lane: the narrowest instantiation that spans the brick's x-window.
+static int mc_columns(const BrickG& b, int mc) {
+  const int need = std::min(b.sdim[0], mc * b.mdim[0] + 2);
+  for (int p : {2, 3, 5, 9})
+    if (need <= 64 * p) return p;
+  return 17;  // wider bricks: runs of x-chunks
 }
 
 template <typename T>
-static void launch_mc_t(const void* linear, const BrickG& b, int mc, float2* ranges, hipStream_t st) {
-  // columns per lane: the narrowest instantiation that spans the brick's x-window
-  const int need = std::min(b.sdim[0], mc * b.mdim[0] + 2);
-  if (need <= 64 * 2)
-    launch_mc<T, 2, 4>(linear, b, mc, ranges, st);
-  else if (need <= 64 * 3)
-    launch_mc<T, 3, 4>(linear, b, mc, ranges, st);
-  else if (need <= 64 * 5)
-    launch_mc<T, 5, 4>(linear, b, mc, ranges, st);
-  else if (need <= 64 * 9)
-    launch_mc<T, 9, 2>(linear, b, mc, ranges, st);
-  else
-    launch_mc<T, 17, 1>(linear, b, mc, ranges, st);  // wider bricks: runs of x-chunks
+static void launch_mc_t(const McBrick* bricks, const std::vector<int>& ids, int mc, hipStream_t st) {
+  for (int p : {2, 3, 5, 9, 17}) {
+    std::vector<int> sel;
+    for (int i : ids)
+      if (mc_columns(bricks[i].view, mc) == p) sel.push_back(i);
+    if (sel.empty()) continue;
+    if (p == 2) launch_mc<T, 2, 4>(bricks, sel.data(), (int)sel.size(), mc, st);
+    if (p == 3) launch_mc<T, 3, 4>(bricks, sel.data(), (int)sel.size(), mc, st);
+    if (p == 5) launch_mc<T, 5, 4>(bricks, sel.data(), (int)sel.size(), mc, st);
+    if (p == 9) launch_mc<T, 9, 2>(bricks, sel.data(), (int)sel.size(), mc, st);
+    if (p == 17) launch_mc<T, 17, 1>(bricks, sel.data(), (int)sel.size(), mc, st);
+  }
 }
 
-hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st) {
-  if (f16)
-    launch_mc_t<__half>(linear, b, mc, ranges, st);
-  else
-    launch_mc_t<float>(linear, b, mc, ranges, st);
+hipError_t launch_macrocells(const McBrick* bricks, int n, int mc, hipStream_t st) {
+  std::vector<int> f32, f16;
+  for (int i = 0; i < n; ++i) (bricks[i].f16 ? f16 : f32).push_back(i);
+  if (!f32.empty()) launch_mc_t<float>(bricks, f32, mc, st);
+  if (!f16.empty()) launch_mc_t<__half>(bricks, f16, mc, st);
   return hipGetLastError();
 }
 
-hipError_t launch_majorants(const float2* ranges, int count, const float4* tf, int ntf, float lo, float hi,
-                            float* maj, hipStream_t st) {
-  hipLaunchKernelGGL(majorant_kernel, dim3((count + 255) / 256), dim3(256), 0, st, ranges, count, tf, ntf, lo, hi,
-                     maj);
+hipError_t launch_majorants(const MajJobs& jobs, const float4* tf, int ntf, float lo, float hi, hipStream_t st) {
+  long long total = 0;
+  for (int j = 0; j < jobs.n; ++j) total += jobs.count[j];
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(majorant_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, jobs, tf, ntf, lo, hi);
   return hipGetLastError();
 }
 

@@ -9,9 +9,24 @@ namespace dpr {
 
 hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
                            int bz, hipStream_t st);
-hipError_t launch_macrocells(const void* linear, const BrickG& b, bool f16, int mc, float2* ranges, hipStream_t st);
-hipError_t launch_majorants(const float2* ranges, int count, const float4* tf, int ntf, float lo, float hi,
-                            float* maj, hipStream_t st);
+// Macrocell ranges of several bricks (linear stored copy, device view, output):
+// one launch per element type and column count.
+struct McBrick {
+  const void* linear;
+  BrickG view;
+  float2* ranges;
+  bool f16;
+};
+hipError_t launch_macrocells(const McBrick* bricks, int n, int mc, hipStream_t st);
+// Majorants of up to kMajJobs bricks in one launch (passed by value).
+constexpr int kMajJobs = 32;
+struct MajJobs {
+  const float2* ranges[kMajJobs];
+  float* maj[kMajJobs];
+  int count[kMajJobs];
+  int n;
+};
+hipError_t launch_majorants(const MajJobs& jobs, const float4* tf, int ntf, float lo, float hi, hipStream_t st);
 hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, const float4* tf, bool f16, bool skip,
                         float4* rgba, float* depth, int* count, hipStream_t st);
 

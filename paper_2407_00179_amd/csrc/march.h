@@ -184,7 +184,8 @@ __device__ __forceinline__ bool shade(const SceneG& sc, const float4* __restrict
 // after every segment that changed T).
 template <typename T, bool SKIP, bool WIDE>
 __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
-                                            const float4* __restrict__ tfs, RayState& r, int budget) {
+                                            const float4* __restrict__ tfs, RayState& r, int budget,
+                                            int min_lanes = 0) {
   const float Ddt = sc.density * sc.dt_f;
   int s = r.s;
   int n = r.n;
@@ -194,6 +195,9 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
   double tau_acc = r.tau;
   bool done = false;
   while (!done && s <= r.s1 && budget > 0) {
+    // at a run boundary: return early (unfinished) once fewer than min_lanes lanes
+    // of the wave are still marching, so the caller can refill the idle ones
+    if (__popcll(__ballot(1)) < min_lanes) break;
     int run = min(r.s1 - s + 1, budget);
     bool empty = false;
     if (SKIP) {

@@ -148,13 +148,28 @@ BrickG Brick::device_view(bool with_majorant, bool force_wide) const {
 }
 
 dpr_status ensure_majorants(dpr_world_t* w) {
+  // bricks whose majorants predate the current TF, up to kMajJobs per launch
+  MajJobs jobs{};
+  Brick* pend[kMajJobs];
+  auto flush = [&]() -> dpr_status {
+    if (!jobs.n) return DPR_OK;
+    DPR_HIP(launch_majorants(jobs, w->tf_dev, w->ntf, w->tf_lo, w->tf_hi, w->dev->stream));
+    for (int j = 0; j < jobs.n; ++j) pend[j]->maj_tf_version = w->tf_version;
+    jobs.n = 0;
+    return DPR_OK;
+  };
   for (auto& b : w->bricks) {
     if (b.maj_tf_version == w->tf_version) continue;
-    int count = b.mdim[0] * b.mdim[1] * b.mdim[2];
-    DPR_HIP(launch_majorants(b.ranges, count, w->tf_dev, w->ntf, w->tf_lo, w->tf_hi, b.maj, w->dev->stream));
-    b.maj_tf_version = w->tf_version;
+    jobs.ranges[jobs.n] = b.ranges;
+    jobs.maj[jobs.n] = b.maj;
+    jobs.count[jobs.n] = b.mdim[0] * b.mdim[1] * b.mdim[2];
+    pend[jobs.n++] = &b;
+    if (jobs.n == kMajJobs) {
+      dpr_status st = flush();
+      if (st != DPR_OK) return st;
+    }
   }
-  return DPR_OK;
+  return flush();
 }
 
 // Composite tables are cached per (frames, ids) so repeated composites of the same
@@ -501,9 +516,10 @@ dpr_status dpr_world_commit(dpr_world w) {
     for (int a = 0; a < 3; ++a) b.mdim[a] = md[a];
     b.mc = mc;
     b.maj_tf_version = 0;
-    BrickG g = b.device_view(false);
-    DPR_HIP(launch_macrocells(b.linear, g, b.dtype == DPR_F16, mc, b.ranges, w->dev->stream));
   }
+  std::vector<McBrick> mcb;
+  for (auto& b : w->bricks) mcb.push_back({b.linear, b.device_view(false), b.ranges, b.dtype == DPR_F16});
+  DPR_HIP(launch_macrocells(mcb.data(), (int)mcb.size(), mc, w->dev->stream));
   // (stream-ordered: later renders on the device stream see the new data; the
   // host does not wait)
   w->committed = true;
