@@ -45,7 +45,7 @@ constexpr int kRefillLanes = 32;
 __global__ void reset_head_kernel(int* head) { *head = 0; }
 
 template <typename T, bool SKIP, bool WIDE>
-__global__ __launch_bounds__(256) void batch_march_kernel(SceneG sc, BatchG bg, const float4* __restrict__ tf) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void batch_march_kernel(SceneG sc, BatchG bg, const float4* __restrict__ tf) {
   extern __shared__ float4 tf_lds[];
   float4* tfb = tf_lds;
   float4* tfs = tf_lds + sc.ntf;

@@ -16,6 +16,7 @@
 namespace dpr {
 
 constexpr double kFix = 4294967296.0;  // 2^32
+constexpr int kShadeRun = 8;            // samples per run in a non-empty macrocell (even)
 
 struct RayState {
   int64_t p[3];          // sample point of segment s, 32.32 fixed point (global voxel-centre coords)
@@ -194,6 +195,10 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
   float tr = r.T, cr = r.cr, cg = r.cg, cb = r.cb;
   double tau_acc = r.tau;
   bool done = false;
+  // ga holds the voxels of the current sample point when pre is set: a run of even
+  // length ends with the next sample's gather in ga, and the next run reuses it
+  Gather<T> ga, gb;
+  bool pre = false;
   while (!done && s <= r.s1 && budget > 0) {
     // at a run boundary: return early (unfinished) once fewer than min_lanes lanes
     // of the wave are still marching, so the caller can refill the idle ones
@@ -203,23 +208,33 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
     if (SKIP) {
       // macrocell of the current sample point: cell = floor(g + 1/2)
       const int64_t half = 0x80000000ll;
-      int m[3];
       const int64_t pp[3] = {p0, p1, p2};
-      const int64_t dd[3] = {d0, d1, d2};
+      int m[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const int cell = (int)((pp[a] + half) >> 32);
-        int ma = (cell - b.olo[a]) >> b.mc_shift;
-        ma = min(max(ma, 0), b.mdim[a] - 1);
-        m[a] = ma;
-        // fixed-point bounds of this macrocell's sample points (outer cells unbounded)
-        const int64_t blo = (ma == 0) ? INT64_MIN
-                                      : ((int64_t)(b.olo[a] + (ma << b.mc_shift)) << 32) - half;
-        const int64_t bhi = (ma == b.mdim[a] - 1) ? INT64_MAX
-                                                  : ((int64_t)(b.olo[a] + ((ma + 1) << b.mc_shift)) << 32) - half;
-        run = min(run, 1 + steps_inside(pp[a], dd[a], blo, bhi, run - 1));
+        m[a] = min(max((cell - b.olo[a]) >> b.mc_shift, 0), b.mdim[a] - 1);
       }
       empty = b.majorant[(m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]] == 0.f;
+      if (empty) {
+        // exactly the samples left inside this empty macrocell (outer cells unbounded)
+        const int64_t dd[3] = {d0, d1, d2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int ma = m[a];
+          const int64_t blo = (ma == 0) ? INT64_MIN
+                                        : ((int64_t)(b.olo[a] + (ma << b.mc_shift)) << 32) - half;
+          const int64_t bhi = (ma == b.mdim[a] - 1) ? INT64_MAX
+                                                    : ((int64_t)(b.olo[a] + ((ma + 1) << b.mc_shift)) << 32) - half;
+          run = min(run, 1 + steps_inside(pp[a], dd[a], blo, bhi, run - 1));
+        }
+      } else {
+        // a non-empty macrocell: a fixed number of samples, then look again.  The
+        // run may cross into other macrocells; shading is correct everywhere (a
+        // sample of zero opacity changes nothing), so its length needs no exact
+        // boundary arithmetic and the lanes of a wave stay in step
+        run = min(run, kShadeRun);
+      }
     }
     if (empty) {  // every sample in the run has opacity exactly 0
       s += run;
@@ -228,6 +243,7 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
       p0 += (int64_t)run * d0;
       p1 += (int64_t)run * d1;
       p2 += (int64_t)run * d2;
+      pre = false;
       continue;
     }
     budget -= run;
@@ -242,8 +258,7 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
       ++s;
       return shade<T>(sc, tfb, tfs, g, Dl, tau_acc, tr, cr, cg, cb);
     };
-    Gather<T> ga, gb;
-    {
+    if (!pre) {
       const int64_t pc[3] = {p0, p1, p2};
       gather<T, WIDE>(sc, b, pc, ga);
     }
@@ -273,6 +288,7 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
       }
       if (++i >= run) break;
     }
+    pre = (run & 1) == 0;
   }
   // the fixed-point position always corresponds to segment s
   r.s = s;
