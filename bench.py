@@ -51,10 +51,10 @@ OPS_PER_SAMPLE = 60
 #     from a plain 256 MiB device-to-device copy in the same runs);
 #   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
 MARCH_COUNTERS = {
-    "sources_sha256": "25f871008ca97ac479326e1e0f608d548f943c03e172168f14cbb4933b69e31a",
-    "traffic_bytes_per_launch": 334707461,
-    "fetch_kib": 156232, "write_kib": 14447, "fetch_scale": 1.9997, "write_scale": 1.0,
-    "valu_lane_instr_per_sample": 162.9,
+    "sources_sha256": "fbd6f8e0f9e2c6853d79253023bae31f1f0a01a79d9ec3692817b4131315cdce",
+    "traffic_bytes_per_launch": 352929843,
+    "fetch_kib": 161708, "write_kib": 21296, "fetch_scale": 1.9997, "write_scale": 1.0,
+    "valu_lane_instr_per_sample": 61.5,
 }
 
 

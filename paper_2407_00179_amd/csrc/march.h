@@ -16,7 +16,7 @@
 namespace dpr {
 
 constexpr double kFix = 4294967296.0;  // 2^32
-constexpr int kShadeRun = 8;            // samples per run in a non-empty macrocell (even)
+constexpr int kShadeRun = 4;            // samples per run in a non-empty macrocell (even)
 
 struct RayState {
   int64_t p[3];          // sample point of segment s, 32.32 fixed point (global voxel-centre coords)
