@@ -186,3 +186,58 @@ def test_render_frame_paths_and_timings(gpu_lib, dpr):
     assert np.array_equal(ra, rb) and np.array_equal(za, zb)
     assert np.array_equal(ra, rc) and np.array_equal(za, zc)
     w.release()
+
+
+def test_batch_empty_views_and_tiny_frames(gpu_lib, dpr):
+    """A camera that sees no brick (no items for it), next to ones that do, and a
+    1x1 frame: every path gives empty fragments where nothing is hit and equals
+    render_frame elsewhere."""
+    dims, vol, boxes, tf = _scene()
+    prm = RenderParams(0.5, 0.99, 25.0)
+    cams = _cams(dims)[:2]
+    # every brick behind the eye: the whole screen is queued, every ray misses
+    behind = Camera((-1.0, -1.0, -1.0), (-2.0, -2.5, -3.0), (0.0, 0.0, 1.0), 40.0, 33, 21)
+    # the volume in front of the eye but outside the view: no item at all
+    aside = Camera((-5.0, 5.0, 0.4), (0.0, 5.0, 0.4), (0.0, 0.0, 1.0), 30.0, 29, 17)
+    tiny = Camera(cams[0].eye, cams[0].center, cams[0].up, 30.0, 1, 1)
+    cams = [cams[0], behind, cams[1], aside, tiny]
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    ref = _reference(dpr, gpu_lib, w, cams)
+    for c in (1, 3):
+        assert np.all(ref[c][0] == 0.0) and np.all(np.isinf(ref[c][1]))
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    for flags in (0, dpr.FLAG_NO_GRAPH, dpr.FLAG_PLAIN):
+        for f in frames:
+            f.rgba.fill_(-1.0)
+            f.depth.fill_(-1.0)
+        w.render_batch(cams, frames, flags)
+        for c, f in enumerate(frames):
+            got = frame_np(f)[:2]
+            assert np.array_equal(got[0], ref[c][0]) and np.array_equal(got[1], ref[c][1]), (flags, c)
+    # only the camera whose view holds no brick: an empty item queue
+    frames[3].rgba.fill_(-1.0)
+    w.render_batch([aside], [frames[3]])
+    got = frame_np(frames[3])[:2]
+    assert np.all(got[0] == 0.0) and np.all(np.isinf(got[1]))
+    w.release()
+
+
+def test_batch_refresh_after_recommit(gpu_lib, dpr):
+    """Same geometry, new macrocell size and a recommit: the cached batch refreshes
+    its brick views (new macrocell grids) and matches a freshly built world."""
+    dims, vol, boxes, tf = _scene()
+    prm = RenderParams(0.5, 0.99, 25.0)
+    cams = _cams(dims)[:2]
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    w.render_batch(cams, frames)
+    w.set_params(dpr.Params(0.5, 0.99, 4, 0))
+    w.commit()
+    w.render_batch(cams, frames)
+    got = [frame_np(f)[:2] for f in frames]
+    w2 = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=4)
+    want = _reference(dpr, gpu_lib, w2, cams)
+    for c in range(len(cams)):
+        assert np.array_equal(got[c][0], want[c][0]) and np.array_equal(got[c][1], want[c][1]), c
+    w.release()
+    w2.release()
