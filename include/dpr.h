@@ -227,6 +227,40 @@ dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
  * the last batched render was a graph replay (or there was none).             */
 dpr_status dpr_batch_timings(dpr_world, float* march_ms, float* composite_ms);
 
+/* ---------------------------------------------------------------- deep frames */
+/* Section 5.1.1 lets a rank emit possibly several RGBA-z fragments per pixel;
+ * section 2.1 (and the interleaved partition of Fig. 6) shows why one is not
+ * enough once a rank's data is not convex.  A deep frame holds, per pixel, a
+ * fragment count (int32) and up to `capacity` layers of premultiplied RGBA
+ * (float4), depth (float) and an intrinsic fragment id (int32), all layer-major:
+ * layer i of pixel p sits at index i * w * h + p.  A pixel's fragments occupy
+ * layers 0 .. count-1 in front-to-back (depth, id) order; later layers hold
+ * unspecified values.  The frame also records the rank that rendered it.
+ * 1 <= capacity <= 255.                                                        */
+typedef struct dpr_deep_frame_t* dpr_deep_frame;
+dpr_status dpr_deep_frame_create(dpr_device, int32_t w, int32_t h, int32_t capacity, dpr_deep_frame* out);
+/* Borrow caller device buffers: counts (w*h int32), rgba (capacity*w*h*4 float),
+ * depth (capacity*w*h float), ids (capacity*w*h int32); they must outlive the
+ * frame.                                                                       */
+dpr_status dpr_deep_frame_wrap(dpr_device, int32_t w, int32_t h, int32_t capacity, int32_t* counts, float* rgba,
+                               float* depth, int32_t* ids, dpr_deep_frame* out);
+void dpr_deep_frame_release(dpr_deep_frame);
+/* Render every brick of the world for its camera into a deep frame: per pixel one
+ * fragment per brick the ray hits (the fragment dpr_render_partial gives), id =
+ * rank * 65536 + brick index, sorted by (depth, id).  The world's bricks may form
+ * any non-convex set.  0 <= rank < 32768; the frame's size is the camera's and
+ * its capacity is at least the world's brick count, so no pixel can overflow.
+ * Runs the batched renderer's march, then a per-tile pass that writes each
+ * pixel's sorted fragment list (enqueued directly, or replayed from a HIP graph
+ * as dpr_render_batch does; DPR_FLAG_NO_GRAPH in the render parameters).       */
+dpr_status dpr_render_deep(dpr_world, int32_t rank, dpr_deep_frame out);
+/* Merge k deep frames per pixel by (depth, id) and composite front to back into
+ * `out`, with the "over" of dpr_composite; depth = the nearest fragment's.  The
+ * parts come from distinct ranks (dpr_render_deep), have out's size, and their
+ * capacities sum to at most 256.  The result does not depend on the order of
+ * `parts`.                                                                     */
+dpr_status dpr_composite_deep(dpr_device, const dpr_deep_frame* parts, int32_t k, dpr_frame out);
+
 /* ---------------------------------------------------------------- training */
 /* Differentiable render of one whole volume (no bricks, ERT off) for n cameras.
  * volume: FP32 device grid of dims (x fastest); tf: n_tf RGBA FP32 (device).

@@ -118,6 +118,47 @@ class Frame:
             pass
 
 
+class DeepFrame:
+    """Deep (multi-fragment) frame in torch tensors borrowed by the library: per
+    pixel a fragment count and up to ``capacity`` layers of premultiplied RGBA,
+    depth and intrinsic fragment id, layer-major (shape (capacity, H, W, ...)); a
+    pixel's fragments fill layers 0..count-1 front to back."""
+
+    def __init__(self, dev: Device, width, height, capacity):
+        torch = _torch()
+        self.dev = dev
+        self.width, self.height, self.capacity = int(width), int(height), int(capacity)
+        d = dev.torch_device
+        self.counts = torch.zeros((self.height, self.width), dtype=torch.int32, device=d)
+        self.rgba = torch.empty((self.capacity, self.height, self.width, 4), dtype=torch.float32, device=d)
+        self.depth = torch.empty((self.capacity, self.height, self.width), dtype=torch.float32, device=d)
+        self.ids = torch.empty((self.capacity, self.height, self.width), dtype=torch.int32, device=d)
+        h = C.c_void_p()
+        check(lib.dpr_deep_frame_wrap(dev.h, self.width, self.height, self.capacity,
+                                      C.c_void_p(self.counts.data_ptr()), C.c_void_p(self.rgba.data_ptr()),
+                                      C.c_void_p(self.depth.data_ptr()), C.c_void_p(self.ids.data_ptr()),
+                                      C.byref(h)))
+        self.h = h
+
+    def release(self):
+        if self.h:
+            lib.dpr_deep_frame_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def composite_deep(dev: Device, parts, out: Frame):
+    """Merge deep frames of distinct ranks per pixel and composite into ``out``."""
+    k = len(parts)
+    fr = (C.c_void_p * k)(*[f.h.value for f in parts])
+    check(lib.dpr_composite_deep(dev.h, fr, k, out.h))
+
+
 def _as_bytes_ptr(arr, dev):
     """Host numpy array or device torch tensor -> (pointer, on_device, dtype code, keepalive)."""
     torch = _torch()
@@ -186,6 +227,10 @@ class World:
 
     def render_frame(self, frame: Frame):
         check(lib.dpr_render_frame(self.h, frame.h))
+
+    def render_deep(self, rank, deep: "DeepFrame"):
+        """Every brick of this world into ``deep`` (fragment ids rank * 65536 + brick)."""
+        check(lib.dpr_render_deep(self.h, int(rank), deep.h))
 
     def render_batch(self, cams, frames, flags=0):
         arr = (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])

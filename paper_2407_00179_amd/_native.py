@@ -78,6 +78,11 @@ _SIGS = {
     "dpr_autotune_batch": ([P, P, C.c_int32, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "dpr_set_batch_tile": ([P, C.c_int32, C.c_int32], C.c_int),
     "dpr_batch_timings": ([P, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
+    "dpr_deep_frame_create": ([P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(P)], C.c_int),
+    "dpr_deep_frame_wrap": ([P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.POINTER(P)], C.c_int),
+    "dpr_deep_frame_release": ([P], None),
+    "dpr_render_deep": ([P, C.c_int32, P], C.c_int),
+    "dpr_composite_deep": ([P, P, C.c_int32, P], C.c_int),
     "dpr_train_workspace_size": ([I64x3, P, C.c_int32, C.c_float, C.POINTER(C.c_size_t)], C.c_int),
     "dpr_render_train_forward": ([P, P, I64x3, P, C.c_int32, C.c_float, C.c_float, C.c_float,
                                   C.POINTER(RenderParams), P, C.c_int32, P, P, P, C.c_size_t], C.c_int),

@@ -25,11 +25,13 @@ struct CompLDS {
   unsigned char order[KMAX];
 };
 
+// Steps 1-3 of the per-wave compositor: stage the depths, order the sources for
+// the tile, and leave each lane's live fragments sorted by (depth, id rank) in
+// s.lst[0 .. n-1][lane]; returns n.
 // depth_of(k): depth of source k at this lane's pixel (only called for live lanes);
-// rgba_of(k): its RGBA; rank_of(k): id rank of source k (distinct per source).
-template <int KMAX, typename DepthF, typename RgbaF, typename RankF>
-__device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool live_px, DepthF depth_of,
-                                               RgbaF rgba_of, RankF rank_of, float4& out, float& out_z) {
+// rank_of(k): id rank of source k (distinct per source).
+template <int KMAX, typename DepthF, typename RankF>
+__device__ __forceinline__ int sort_wave(CompLDS<KMAX>& s, int K, bool live_px, DepthF depth_of, RankF rank_of) {
   const int lane = threadIdx.x & 63;
   for (int k = lane; k < K; k += 64) {
     s.rank[k] = rank_of(k);
@@ -91,6 +93,16 @@ __device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool liv
     }
     ++n;
   }
+  return n;
+}
+
+// depth_of(k): depth of source k at this lane's pixel (only called for live lanes);
+// rgba_of(k): its RGBA; rank_of(k): id rank of source k (distinct per source).
+template <int KMAX, typename DepthF, typename RgbaF, typename RankF>
+__device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool live_px, DepthF depth_of,
+                                               RgbaF rgba_of, RankF rank_of, float4& out, float& out_z) {
+  const int lane = threadIdx.x & 63;
+  const int n = sort_wave<KMAX>(s, K, live_px, depth_of, rank_of);
   // 4. front-to-back over, RGBA fetched for live fragments only
   float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f;
   constexpr int F = KMAX < 16 ? 8 : 16;  // RGBA loads in flight per lane

@@ -184,6 +184,55 @@ __global__ __launch_bounds__(64) void tile_composite_kernel(BatchG bg, const int
   }
 }
 
+// Deep-frame target of the tile pass (dpr_render_deep): per pixel the count and
+// the sorted fragments, layer-major (layer i of pixel p at i * P + p).
+struct DeepOut {
+  int* counts;
+  float4* rgba;
+  float* depth;
+  int* ids;
+  size_t P;
+  int rank;
+};
+
+// Per camera tile: sort each pixel's fragments of the items covering the tile by
+// (depth, brick) and write them as the pixel's deep-frame layers.  One wave per 64
+// pixels of a tile; one camera.
+template <int KMAX>
+__global__ __launch_bounds__(64) void tile_deep_kernel(BatchG bg, const int* __restrict__ tile_xy,
+                                                       const int* __restrict__ tile_off,
+                                                       const int* __restrict__ tile_items, DeepOut dout,
+                                                       int chunks) {
+  __shared__ CompLDS<KMAX> s;
+  const int g = blockIdx.x / chunks;
+  const int q = blockIdx.x % chunks;
+  const int lane = threadIdx.x;
+  const CamG& cam = bg.cams[0];
+  const int tp = bg.tile_w * bg.tile_h;
+  const int pix = q * 64 + lane;
+  const int px = tile_xy[2 * g] * bg.tile_w + pix % bg.tile_w;
+  const int py = tile_xy[2 * g + 1] * bg.tile_h + pix / bg.tile_w;
+  const bool live_px = pix < tp && px < cam.W && py < cam.H;
+  const int k0 = tile_off[g];
+  const int K = tile_off[g + 1] - k0;
+  int n = 0;
+  if (K > 0)
+    n = sort_wave<KMAX>(
+        s, K, live_px, [&](int k) { return bg.frag_depth[(size_t)tile_items[k0 + k] * tp + pix]; },
+        [&](int k) { return bg.items[tile_items[k0 + k]].brick; });
+  if (live_px) {
+    const size_t p = (size_t)py * cam.W + px;
+    dout.counts[p] = n;
+    for (int i = 0; i < n; ++i) {
+      const int k = s.lst[i][lane];
+      const int item = tile_items[k0 + k];
+      dout.rgba[(size_t)i * dout.P + p] = bg.frag_rgba[(size_t)item * tp + pix];
+      dout.depth[(size_t)i * dout.P + p] = s.zs[k][lane];
+      dout.ids[(size_t)i * dout.P + p] = dout.rank * 65536 + bg.items[item].brick;
+    }
+  }
+}
+
 struct BatchState {
   // key
   std::vector<dpr_camera> cams;
@@ -192,6 +241,10 @@ struct BatchState {
   int tile_w = 0, tile_h = 0;
   uint64_t geo_version = 0;
   bool skip = true;
+  // deep-frame target (dpr_render_deep) instead of flat frames, and its buffers
+  dpr_deep_frame deep = nullptr;
+  const void* deep_ptrs[4] = {nullptr, nullptr, nullptr, nullptr};
+  int deep_rank = -1;
   // brick views last uploaded to d_bricks, and the scene arguments and TF table
   // baked into the captured graph
   std::vector<BrickG> h_bricks;
@@ -352,15 +405,29 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool
   const int tp = b->tile_w * b->tile_h;
   const int chunks = (tp + 63) / 64;
   dim3 cgrid((unsigned)b->n_tiles * chunks);
-  if (b->max_k <= 16)
-    hipLaunchKernelGGL(tile_composite_kernel<16>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
-                       b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
-  else if (b->max_k <= 64)
-    hipLaunchKernelGGL(tile_composite_kernel<64>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
-                       b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
-  else
-    hipLaunchKernelGGL(tile_composite_kernel<256>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
-                       b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
+  if (b->deep) {
+    const dpr_deep_frame d = b->deep;
+    DeepOut dout{d->counts, d->rgba, d->depth, d->ids, (size_t)d->w * d->h, b->deep_rank};
+    if (b->max_k <= 16)
+      hipLaunchKernelGGL(tile_deep_kernel<16>, cgrid, dim3(64), 0, st, g, b->d_tile_xy, b->d_tile_off,
+                         b->d_tile_items, dout, chunks);
+    else if (b->max_k <= 64)
+      hipLaunchKernelGGL(tile_deep_kernel<64>, cgrid, dim3(64), 0, st, g, b->d_tile_xy, b->d_tile_off,
+                         b->d_tile_items, dout, chunks);
+    else
+      hipLaunchKernelGGL(tile_deep_kernel<256>, cgrid, dim3(64), 0, st, g, b->d_tile_xy, b->d_tile_off,
+                         b->d_tile_items, dout, chunks);
+  } else {
+    if (b->max_k <= 16)
+      hipLaunchKernelGGL(tile_composite_kernel<16>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
+                         b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
+    else if (b->max_k <= 64)
+      hipLaunchKernelGGL(tile_composite_kernel<64>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
+                         b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
+    else
+      hipLaunchKernelGGL(tile_composite_kernel<256>, cgrid, dim3(64), 0, st, g, b->d_tile_cam, b->d_tile_xy,
+                         b->d_tile_off, b->d_tile_items, b->d_out_rgba, b->d_out_depth, chunks);
+  }
   if (timed) (void)hipEventRecord(b->ev[2], st);
   return hipGetLastError();
 }
@@ -375,8 +442,8 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   b->outs.assign(outs, outs + n);
   b->out_ptrs.clear();
   for (int c = 0; c < n; ++c) {
-    b->out_ptrs.push_back(outs[c]->rgba);
-    b->out_ptrs.push_back(outs[c]->depth);
+    b->out_ptrs.push_back(outs[c] ? outs[c]->rgba : nullptr);
+    b->out_ptrs.push_back(outs[c] ? outs[c]->depth : nullptr);
   }
   b->tile_w = tw;
   b->tile_h = th;
@@ -445,8 +512,8 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   std::vector<float4*> orgba(n);
   std::vector<float*> odepth(n);
   for (int c = 0; c < n; ++c) {
-    orgba[c] = (float4*)outs[c]->rgba;
-    odepth[c] = outs[c]->depth;
+    orgba[c] = outs[c] ? (float4*)outs[c]->rgba : nullptr;
+    odepth[c] = outs[c] ? outs[c]->depth : nullptr;
   }
   dpr_status s;
   if ((s = upload(&b->d_cams, cg, st, "batch cameras")) != DPR_OK) return s;
@@ -520,13 +587,24 @@ static dpr_status refresh_batch(dpr_world w, BatchState* b) {
   return DPR_OK;
 }
 
+static void deep_key(dpr_deep_frame d, const void* ptrs[4]) {
+  ptrs[0] = d ? d->counts : nullptr;
+  ptrs[1] = d ? d->rgba : nullptr;
+  ptrs[2] = d ? d->depth : nullptr;
+  ptrs[3] = d ? d->ids : nullptr;
+}
+
 static bool same_key(const BatchState* b, dpr_world w, const dpr_camera* cams, int n, const dpr_frame* outs, int tw,
-                     int th) {
+                     int th, dpr_deep_frame deep, int rank) {
   if (!b || b->tile_w != tw || b->tile_h != th || (int)b->cams.size() != n) return false;
+  const void* dp[4];
+  deep_key(deep, dp);
+  if (b->deep != deep || b->deep_rank != rank || memcmp(b->deep_ptrs, dp, sizeof(dp)) != 0) return false;
   if (b->geo_version != w->geo_version || b->skip != !(w->params.flags & DPR_FLAG_NO_SKIP)) return false;
   if (memcmp(b->cams.data(), cams, n * sizeof(dpr_camera)) != 0) return false;
   for (int c = 0; c < n; ++c)
-    if (b->outs[c] != outs[c] || b->out_ptrs[2 * c] != outs[c]->rgba || b->out_ptrs[2 * c + 1] != outs[c]->depth)
+    if (b->outs[c] != outs[c] || (outs[c] && (b->out_ptrs[2 * c] != outs[c]->rgba ||
+                                              b->out_ptrs[2 * c + 1] != outs[c]->depth)))
       return false;
   return b->d_items != nullptr;
 }
@@ -589,14 +667,17 @@ static dpr_status render_plain(dpr_world w, const dpr_camera* cams, int n, dpr_f
 }
 
 static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n, dpr_frame* outs, uint32_t flags,
-                                     int tw, int th) {
+                                     int tw, int th, dpr_deep_frame deep = nullptr, int rank = -1) {
   if (!w->batch) w->batch = new BatchState;
   BatchState* b = w->batch;
   dpr_status s = ensure_majorants(w);
   if (s != DPR_OK) return s;
-  if (!same_key(b, w, cams, n, outs, tw, th)) {
+  if (!same_key(b, w, cams, n, outs, tw, th, deep, rank)) {
     s = build_batch(w, b, cams, n, outs, tw, th);
     if (s != DPR_OK) return s;
+    b->deep = deep;
+    b->deep_rank = rank;
+    deep_key(deep, b->deep_ptrs);
   } else {
     s = refresh_batch(w, b);
     if (s != DPR_OK) return s;
@@ -620,6 +701,15 @@ dpr_status render_frame_batched(dpr_world w, dpr_frame out) {
                             w->batch_tile_h);
 }
 
+static dpr_status render_deep(dpr_world w, int rank, dpr_deep_frame out) {
+  dpr_frame none = nullptr;
+  dpr_status s = render_batch_tiled(w, &w->cam, 1, &none, w->params.flags & DPR_FLAG_NO_GRAPH, w->batch_tile_w,
+                                    w->batch_tile_h, out, rank);
+  if (s != DPR_OK) return s;
+  out->rank = rank;
+  return DPR_OK;
+}
+
 }  // namespace dpr
 
 using namespace dpr;
@@ -635,6 +725,24 @@ dpr_status dpr_render_batch(dpr_world w, const dpr_camera* cams, int32_t n, dpr_
     return render_plain(w, cams, n, outs);
   }
   return render_batch_tiled(w, cams, n, outs, flags, w->batch_tile_w, w->batch_tile_h);
+}
+
+dpr_status dpr_render_deep(dpr_world w, int32_t rank, dpr_deep_frame out) {
+  if (!w || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_deep: NULL argument");
+  if (!w->committed) return fail(DPR_ERR_INVALID_STATE, "dpr_render_deep: world not committed");
+  if (!w->tf_set) return fail(DPR_ERR_INVALID_STATE, "dpr_render_deep: no transfer function set");
+  if (!w->cam_set) return fail(DPR_ERR_INVALID_STATE, "dpr_render_deep: no camera set");
+  if (rank < 0 || rank >= 32768) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_deep: rank %d", rank);
+  if (out->dev != w->dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_deep: frame of another device");
+  if (out->w != w->cam.width || out->h != w->cam.height)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_deep: frame %dx%d != camera %dx%d", out->w, out->h,
+                w->cam.width, w->cam.height);
+  if (out->cap < (int)w->bricks.size())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_deep: capacity %d < %d bricks", out->cap,
+                (int)w->bricks.size());
+  for (const auto& b : w->bricks)
+    if (b.dtype != w->bricks[0].dtype) return fail(DPR_ERR_UNSUPPORTED, "dpr_render_deep: bricks of mixed dtypes");
+  return render_deep(w, rank, out);
 }
 
 dpr_status dpr_batch_timings(dpr_world w, float* march_ms, float* composite_ms) {

@@ -16,6 +16,8 @@
 // the same arithmetic, so it gets the same bits: for up to 16 sources in place, by
 // repeated selection of its next fragment; for more, through a fix-up list that a
 // second pass works off with the fully general per-wave sort (composite_wave).
+#include <algorithm>
+
 #include "composite.h"
 #include "device_common.h"
 #include "kernels.h"
@@ -323,6 +325,65 @@ static void launch_k(const CompTable* tab, int k, int n_pixels, float4* out_rgba
   if constexpr (KMAX > 16)
     hipLaunchKernelGGL(composite_fixup_kernel<KMAX>, dim3(cu_count), dim3(64), 0, st, tab, k, out_rgba, out_depth,
                        fix_count, fix_list);
+}
+
+// Merge of deep-frame layers: source k is layer[k] of a frame with per-pixel
+// counts count[k], live where layer[k] < count[k][p].  One wave per 64 pixels,
+// persistent over the frame, general per-wave sort (composite_wave).
+template <int KMAX>
+__global__ __launch_bounds__(64) void composite_deep_kernel(const CompTable* __restrict__ tab, int K, int P,
+                                                            float4* __restrict__ out_rgba,
+                                                            float* __restrict__ out_depth) {
+  __shared__ CompLDS<KMAX> s;
+  __shared__ const float4* prgba[KMAX];
+  __shared__ const float* pdepth[KMAX];
+  __shared__ const int* pcount[KMAX];
+  __shared__ int player[KMAX];
+  const int lane = threadIdx.x;
+  for (int k = lane; k < K; k += 64) {
+    prgba[k] = tab->rgba[k];
+    pdepth[k] = tab->depth[k];
+    pcount[k] = tab->count[k];
+    player[k] = tab->layer[k];
+  }
+  __syncthreads();
+  for (int base = blockIdx.x * 64; base < P; base += gridDim.x * 64) {
+    const int p = base + lane;
+    const bool live = p < P;
+    float4 c;
+    float z;
+    composite_wave<KMAX>(
+        s, K, live, [&](int k) { return player[k] < pcount[k][p] ? pdepth[k][p] : INFINITY; },
+        [&](int k) { return prgba[k][p]; }, [&](int k) { return tab->idrank[k]; }, c, z);
+    if (live) {
+      out_rgba[p] = c;
+      out_depth[p] = z;
+    }
+    __syncthreads();
+  }
+}
+
+template <int KMAX>
+static void launch_deep_k(const CompTable* tab, int k, int n_pixels, float4* out_rgba, float* out_depth,
+                          int cu_count, hipStream_t st) {
+  const int tiles = (n_pixels + 63) / 64;
+  const int grid = std::max(1, std::min(tiles, cu_count * 8));
+  hipLaunchKernelGGL(composite_deep_kernel<KMAX>, dim3(grid), dim3(64), 0, st, tab, k, n_pixels, out_rgba,
+                     out_depth);
+}
+
+hipError_t launch_composite_deep(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
+                                 int cu_count, hipStream_t st) {
+  if (n_pixels <= 0) return hipSuccess;
+  if (k <= 16)
+    launch_deep_k<16>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
+  else if (k <= 64)
+    launch_deep_k<64>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
+  else if (k <= 128)
+    launch_deep_k<128>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
+  else
+    launch_deep_k<256>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,

@@ -175,14 +175,17 @@ dpr_status ensure_majorants(dpr_world_t* w) {
 // Composite tables are cached per (frames, ids) so repeated composites of the same
 // frames (every dpr_render_frame) issue no host-to-device traffic at all.
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
-                      const std::vector<int32_t>& ids, CompTable** out) {
+                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts,
+                      const std::vector<int>* layers) {
   const size_t k = rgba.size();
   std::vector<uint64_t> key;
-  key.reserve(3 * k);
+  key.reserve(5 * k);
   for (size_t i = 0; i < k; ++i) {
     key.push_back((uint64_t)(uintptr_t)rgba[i]);
     key.push_back((uint64_t)(uintptr_t)depth[i]);
     key.push_back((uint64_t)(uint32_t)ids[i]);
+    key.push_back(counts ? (uint64_t)(uintptr_t)(*counts)[i] : 0);
+    key.push_back(layers ? (uint64_t)(uint32_t)(*layers)[i] : 0);
   }
   auto it = dev->comp_cache.find(key);
   if (it != dev->comp_cache.end()) {
@@ -209,6 +212,8 @@ dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, co
   for (size_t i = 0; i < k; ++i) {
     e.host->rgba[i] = rgba[i];
     e.host->depth[i] = depth[i];
+    e.host->count[i] = counts ? (*counts)[i] : nullptr;
+    e.host->layer[i] = layers ? (*layers)[i] : 0;
   }
   dpr_status st = dev_alloc((void**)&e.dev, sizeof(CompTable), "composite table");
   if (st != DPR_OK) {
@@ -730,6 +735,114 @@ dpr_status dpr_render_partial(dpr_world w, int32_t id, dpr_frame out) {
 
 dpr_status dpr_composite(dpr_device d, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out) {
   return composite_frames(d, parts, ids, k, out);
+}
+
+// ---------------------------------------------------------------- deep frames
+static dpr_status deep_frame_checks(dpr_device d, int32_t wd, int32_t ht, int32_t cap, const char* who) {
+  if (!d) return fail(DPR_ERR_INVALID_ARGUMENT, "%s: NULL device", who);
+  if (wd <= 0 || ht <= 0 || (int64_t)wd * ht > (int64_t)1 << 30)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "%s: size %dx%d", who, wd, ht);
+  if (cap < 1 || cap > 255) return fail(DPR_ERR_INVALID_ARGUMENT, "%s: capacity %d outside [1, 255]", who, cap);
+  return DPR_OK;
+}
+
+dpr_status dpr_deep_frame_create(dpr_device d, int32_t wd, int32_t ht, int32_t cap, dpr_deep_frame* out) {
+  if (!out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_deep_frame_create: NULL out");
+  dpr_status st = deep_frame_checks(d, wd, ht, cap, "dpr_deep_frame_create");
+  if (st != DPR_OK) return st;
+  auto* f = new dpr_deep_frame_t;
+  f->dev = d;
+  f->w = wd;
+  f->h = ht;
+  f->cap = cap;
+  f->owned = true;
+  const size_t px = (size_t)wd * ht, lay = px * cap;
+  if ((st = dev_alloc((void**)&f->counts, px * sizeof(int), "deep frame counts")) != DPR_OK ||
+      (st = dev_alloc((void**)&f->rgba, lay * sizeof(float4), "deep frame rgba")) != DPR_OK ||
+      (st = dev_alloc((void**)&f->depth, lay * sizeof(float), "deep frame depth")) != DPR_OK ||
+      (st = dev_alloc((void**)&f->ids, lay * sizeof(int), "deep frame ids")) != DPR_OK) {
+    dpr_deep_frame_release(f);
+    return st;
+  }
+  *out = f;
+  return DPR_OK;
+}
+
+dpr_status dpr_deep_frame_wrap(dpr_device d, int32_t wd, int32_t ht, int32_t cap, int32_t* counts, float* rgba,
+                               float* depth, int32_t* ids, dpr_deep_frame* out) {
+  if (!out || !counts || !rgba || !depth || !ids)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_deep_frame_wrap: NULL argument");
+  dpr_status st = deep_frame_checks(d, wd, ht, cap, "dpr_deep_frame_wrap");
+  if (st != DPR_OK) return st;
+  auto* f = new dpr_deep_frame_t;
+  f->dev = d;
+  f->w = wd;
+  f->h = ht;
+  f->cap = cap;
+  f->counts = counts;
+  f->rgba = (float4*)rgba;
+  f->depth = depth;
+  f->ids = ids;
+  *out = f;
+  return DPR_OK;
+}
+
+void dpr_deep_frame_release(dpr_deep_frame f) {
+  if (!f) return;
+  if (f->owned) {
+    (void)hipStreamSynchronize(f->dev->stream);
+    dev_free(f->counts);
+    dev_free(f->rgba);
+    dev_free(f->depth);
+    dev_free(f->ids);
+  }
+  delete f;
+}
+
+dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32_t k, dpr_frame out) {
+  if (!dev || !parts || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: NULL argument");
+  if (k < 1) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: k = %d", k);
+  if (out->dev != dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: out belongs to another device");
+  std::vector<const float4*> rg;
+  std::vector<const float*> dp;
+  std::vector<int32_t> id;
+  std::vector<const int*> cnt;
+  std::vector<int> lay, ranks;
+  const size_t P = (size_t)out->w * out->h;
+  for (int j = 0; j < k; ++j) {
+    const dpr_deep_frame f = parts[j];
+    if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: part %d is NULL", j);
+    if (f->dev != dev)
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: part %d belongs to another device", j);
+    if (f->w != out->w || f->h != out->h)
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: part %d is %dx%d, out is %dx%d", j, f->w, f->h,
+                  out->w, out->h);
+    if (f->rank < 0)
+      return fail(DPR_ERR_INVALID_STATE, "dpr_composite_deep: part %d was not rendered by dpr_render_deep", j);
+    if ((int)rg.size() + f->cap > kMaxFrags)
+      return fail(DPR_ERR_UNSUPPORTED, "dpr_composite_deep: capacities sum to more than %d", kMaxFrags);
+    ranks.push_back(f->rank);
+    // source (part, layer).  Ties in depth must order as the fragments' ids: inside
+    // a part the layers are already in (depth, id) order, and ids of different
+    // parts differ in their rank, so ranking the sources by (rank, layer) does it
+    for (int l = 0; l < f->cap; ++l) {
+      rg.push_back(f->rgba + (size_t)l * P);
+      dp.push_back(f->depth + (size_t)l * P);
+      id.push_back(f->rank * 256 + l);
+      cnt.push_back(f->counts);
+      lay.push_back(l);
+    }
+  }
+  std::vector<int> sr = ranks;
+  std::sort(sr.begin(), sr.end());
+  if (std::adjacent_find(sr.begin(), sr.end()) != sr.end())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: the parts must come from distinct ranks");
+  CompTable* tab = nullptr;
+  dpr_status st = comp_table(dev, rg, dp, id, &tab, &cnt, &lay);
+  if (st != DPR_OK) return st;
+  DPR_HIP(launch_composite_deep(tab, (int)rg.size(), (int)P, (float4*)out->rgba, out->depth, dev->cu_count,
+                                dev->stream));
+  return DPR_OK;
 }
 
 dpr_status dpr_render_frame(dpr_world w, dpr_frame out) {

@@ -65,6 +65,17 @@ struct dpr_frame_t {
   bool owned = false;
 };
 
+struct dpr_deep_frame_t {
+  dpr_device dev = nullptr;
+  int w = 0, h = 0, cap = 0;
+  int rank = -1;  // set by dpr_render_deep
+  int* counts = nullptr;
+  float4* rgba = nullptr;
+  float* depth = nullptr;
+  int* ids = nullptr;
+  bool owned = false;
+};
+
 namespace dpr {
 
 struct Brick {
@@ -124,6 +135,7 @@ dpr_status ensure_majorants(dpr_world_t* w);
 dpr_status render_frame_batched(dpr_world w, dpr_frame out);
 dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out);
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
-                      const std::vector<int32_t>& ids, CompTable** out);
+                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts = nullptr,
+                      const std::vector<int>* layers = nullptr);
 
 }  // namespace dpr
