@@ -13,7 +13,8 @@ processed before termination, skipped ones included), in Msamples/s.
 
 Extra sections (same JSON line): the K=128 compositor at 3840x2160, the batched
 persistent renderer against plain per-brick launches on the 27-brick 16-camera
-workload, and the backward/forward time ratio of the differentiable renderer.
+workload, the backward/forward time ratio of the differentiable renderer, and deep
+(multi-fragment) frames of an interleaved 8-rank partition.
 
 The CPU baseline (the FP64 oracle, not tuned) runs first, before any GPU use,
 on a bounded pixel sample of the default workload, over a fork pool of host cores.
@@ -306,6 +307,75 @@ def bench_cfg3(args, dpr, torch, dev):
     return r
 
 
+def bench_deep(args, dpr, torch, dev):
+    """Deep frames: the default 512^3 volume cut into 4x4x4 bricks of 128^3 cells dealt
+    eight to each of 8 ranks at random (every rank's data non-convex), 1024x1024.  Each
+    rank renders its deep frame (batched march + per-pixel fragment lists), then the 8
+    deep frames are merged; both run here one after the other on the one GPU.  The
+    same 64 bricks held by one rank and composited flat give the reference image and
+    time."""
+    cfg = get_config("cfg2")
+    dims = cfg.dims
+    R = 8
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+    tf = make_tf(cfg.seeds["tf"])
+    cam = orbit_camera(dims, *cfg.image)
+    W, H = cam.width, cam.height
+    P = W * H
+    boxes = even_split(dims, (4, 4, 4))
+    perm = np.random.default_rng(cfg.seeds["volume"] + 17).permutation(len(boxes))
+    ranks = [sorted(int(i) for i in perm[r::R]) for r in range(R)]
+
+    def world(ids):
+        w = dpr.World(dev, dims)
+        w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
+        for i in ids:
+            b = extract_brick(vol, dims, *boxes[i], 1)
+            w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)
+        w.commit()
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+        w.set_camera(cam)
+        return w
+
+    worlds = [world(ids) for ids in ranks]
+    deeps = [dpr.DeepFrame(dev, W, H, len(ids)) for ids in ranks]
+    out = dpr.Frame(dev, W, H)
+
+    def render_all():
+        for r in range(R):
+            worlds[r].render_deep(r, deeps[r])
+
+    reps = max(3, args.steps)
+    render_all()
+    dpr.composite_deep(dev, deeps, out)
+    torch.cuda.synchronize()
+    ms_render = _timed(torch, render_all, reps)
+    ms_comp = _timed(torch, lambda: dpr.composite_deep(dev, deeps, out), reps)
+    live = sum(int(d.counts.sum().item()) for d in deeps)
+    max_frags = max(int(d.counts.max().item()) for d in deeps)
+    samples = sum(_count_samples(dpr, dev, worlds[r], [cam], len(ranks[r])) for r in range(R))
+    # the same bricks held by one rank, composited flat
+    flat_w = world(range(len(boxes)))
+    flat = dpr.Frame(dev, W, H)
+    flat_w.render_frame(flat)
+    torch.cuda.synchronize()
+    ms_flat = _timed(torch, lambda: flat_w.render_frame(flat), reps)
+    diff = float((out.rgba - flat.rgba).abs().max().item())
+    alg = R * P * 4 + live * 20 + P * 20
+    for h in worlds + deeps + [out, flat, flat_w]:
+        h.release()
+    torch.cuda.empty_cache()
+    gbs = alg / ms_comp / 1e6
+    return dict(workload="512^3 FP32 volume, 4x4x4 bricks of 128^3 dealt 8 per rank to 8 ranks at random, "
+                         "1024x1024, step 0.5 voxel, ERT 0.99: 8 deep renders + deep composite",
+                samples=samples, ms_render_8_ranks=ms_render, ms_composite_deep=ms_comp,
+                msamples_deep=samples / (ms_render + ms_comp) / 1e3, live_fragments=live,
+                max_fragments_per_pixel=max_frags, composite_algorithmic_bytes=alg, composite_GBps=gbs,
+                composite_frac_hbm=gbs / HBM_PEAK_GBS, ms_one_rank_flat=ms_flat,
+                max_abs_diff_vs_one_rank=diff)
+
+
 def bench_train(args, dpr, torch, dev):
     """256^3 FP32 density grid + 256-entry TF as parameters, 16 cameras at 512x512:
     the differentiable forward (with checkpoint stores) and the adjoint march."""
@@ -370,7 +440,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batch,cfg3,train,composite128")
+    ap.add_argument("--sections", default="batch,cfg3,train,composite128,deep")
     ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (scales HBM byte counters)")
@@ -466,6 +536,9 @@ def main():
     if "train" in secs:
         log("GPU: differentiable render forward/backward")
         line["train_cfg4"] = bench_train(args, dpr, torch, dev)
+    if "deep" in secs:
+        log("GPU: deep frames of an interleaved 8-rank partition")
+        line["deep_8ranks"] = bench_deep(args, dpr, torch, dev)
     if "composite128" in secs:
         log("GPU: K=128 composite at 3840x2160")
         line["composite_k128"] = bench_composite128(args, dpr, torch, dev)

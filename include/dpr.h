@@ -254,11 +254,13 @@ void dpr_deep_frame_release(dpr_deep_frame);
  * pixel's sorted fragment list (enqueued directly, or replayed from a HIP graph
  * as dpr_render_batch does; DPR_FLAG_NO_GRAPH in the render parameters).       */
 dpr_status dpr_render_deep(dpr_world, int32_t rank, dpr_deep_frame out);
-/* Merge k deep frames per pixel by (depth, id) and composite front to back into
- * `out`, with the "over" of dpr_composite; depth = the nearest fragment's.  The
- * parts come from distinct ranks (dpr_render_deep), have out's size, and their
- * capacities sum to at most 256.  The result does not depend on the order of
- * `parts`.                                                                     */
+/* Merge k deep frames per pixel and composite front to back into `out`, with the
+ * "over" of dpr_composite; depth = the nearest fragment's.  Every live fragment
+ * (layer < count) is ranked by (depth, rank of its part, layer), which for frames
+ * of dpr_render_deep is their (depth, id) order.  The parts come from distinct
+ * ranks (dpr_render_deep), have out's size, and 1 <= k <= 256.  A pixel with n
+ * live fragments reads its depths ceil(n / 8) times.  The result does not depend
+ * on the order of `parts`.                                                     */
 dpr_status dpr_composite_deep(dpr_device, const dpr_deep_frame* parts, int32_t k, dpr_frame out);
 
 /* ---------------------------------------------------------------- training */

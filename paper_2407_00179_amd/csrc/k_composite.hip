@@ -327,62 +327,109 @@ static void launch_k(const CompTable* tab, int k, int n_pixels, float4* out_rgba
                        fix_count, fix_list);
 }
 
-// Merge of deep-frame layers: source k is layer[k] of a frame with per-pixel
-// counts count[k], live where layer[k] < count[k][p].  One wave per 64 pixels,
-// persistent over the frame, general per-wave sort (composite_wave).
-template <int KMAX>
-__global__ __launch_bounds__(64) void composite_deep_kernel(const CompTable* __restrict__ tab, int K, int P,
-                                                            float4* __restrict__ out_rgba,
-                                                            float* __restrict__ out_depth) {
-  __shared__ CompLDS<KMAX> s;
-  __shared__ const float4* prgba[KMAX];
-  __shared__ const float* pdepth[KMAX];
-  __shared__ const int* pcount[KMAX];
-  __shared__ int player[KMAX];
-  const int lane = threadIdx.x;
-  for (int k = lane; k < K; k += 64) {
-    prgba[k] = tab->rgba[k];
-    pdepth[k] = tab->depth[k];
-    pcount[k] = tab->count[k];
-    player[k] = tab->layer[k];
+// Merge of deep frames (dpr_composite_deep).  Table entry r describes part r:
+// rgba[r] / depth[r] are its layer-major arrays (layer l of pixel p at l * P + p),
+// count[r] its per-pixel fragment counts, idrank[r] its place in rank order.
+// One thread per pixel.  A fragment's key is (depth, part rank, layer); the thread
+// takes the pixel's fragments in passes, each keeping the kSel nearest keys beyond
+// the last one composited -- in registers, sorted by a branch-free insertion --
+// and compositing them front to back with the same "over" as composite_wave, so a
+// pixel with n live fragments costs ceil(n / kSel) passes over its depths.  The
+// parts' layers need not be sorted for this: every live fragment is ranked.
+constexpr int kSel = 8;
+
+__device__ __forceinline__ bool key_less(float za, int ka, float zb, int kb) {
+  return za < zb || (za == zb && ka < kb);
+}
+
+__global__ __launch_bounds__(256) void deep_merge_kernel(const CompTable* __restrict__ tab, int R, int P,
+                                                         float4* __restrict__ out_rgba,
+                                                         float* __restrict__ out_depth) {
+  __shared__ const float* pdepth[kMaxFrags];
+  __shared__ const int* pcount[kMaxFrags];
+  __shared__ int pkey[kMaxFrags];                  // rank-order index << 8
+  __shared__ const float4* rgba_by_rank[kMaxFrags];
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    const int q = tab->idrank[r];
+    pdepth[r] = tab->depth[r];
+    pcount[r] = tab->count[r];
+    pkey[r] = q << 8;
+    rgba_by_rank[q] = tab->rgba[r];
   }
   __syncthreads();
-  for (int base = blockIdx.x * 64; base < P; base += gridDim.x * 64) {
-    const int p = base + lane;
-    const bool live = p < P;
-    float4 c;
-    float z;
-    composite_wave<KMAX>(
-        s, K, live, [&](int k) { return player[k] < pcount[k][p] ? pdepth[k][p] : INFINITY; },
-        [&](int k) { return prgba[k][p]; }, [&](int k) { return tab->idrank[k]; }, c, z);
-    if (live) {
-      out_rgba[p] = c;
-      out_depth[p] = z;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const size_t sP = (size_t)P;
+  float lz = -INFINITY;  // last key composited
+  int lk = -1;
+  float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f, znear = INFINITY;
+  int done = 0, n = 0;
+  do {
+    float z[kSel];
+    int kk[kSel];
+#pragma unroll
+    for (int j = 0; j < kSel; ++j) {
+      z[j] = INFINITY;
+      kk[j] = 0;
     }
-    __syncthreads();
-  }
+    int m = 0;
+    n = 0;
+    for (int r0 = 0; r0 < R; r0 += 8) {
+      int c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] = r0 + u < R ? pcount[r0 + u][p] : 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        n += c[u];
+        if (c[u] <= 0) continue;
+        const float* dz = pdepth[r0 + u] + p;
+        const int kb = pkey[r0 + u];
+        for (int l = 0; l < c[u]; ++l) {
+          const float d = dz[(size_t)l * sP];
+          const int key = kb | l;
+          if (!key_less(lz, lk, d, key)) continue;                             // composited already
+          if (m == kSel && !key_less(d, key, z[kSel - 1], kk[kSel - 1])) continue;  // beyond this pass
+          int pos = 0;
+#pragma unroll
+          for (int j = 0; j < kSel; ++j) pos += (j < m) && key_less(z[j], kk[j], d, key);
+#pragma unroll
+          for (int j = kSel - 1; j > 0; --j) {
+            z[j] = j > pos ? z[j - 1] : (j == pos ? d : z[j]);
+            kk[j] = j > pos ? kk[j - 1] : (j == pos ? key : kk[j]);
+          }
+          if (pos == 0) {
+            z[0] = d;
+            kk[0] = key;
+          }
+          m = m < kSel ? m + 1 : kSel;
+        }
+      }
+    }
+    if (done == 0 && m > 0) znear = z[0];
+#pragma unroll
+    for (int j = 0; j < kSel; ++j) {
+      if (j < m) {
+        const float4 f = rgba_by_rank[kk[j] >> 8][(size_t)(kk[j] & 255) * sP + p];
+        cr = fmaf(tr, f.x, cr);
+        cg = fmaf(tr, f.y, cg);
+        cb = fmaf(tr, f.z, cb);
+        ca = fmaf(tr, f.w, ca);
+        tr *= 1.f - f.w;
+        lz = z[j];
+        lk = kk[j];
+      }
+    }
+    done += m;
+  } while (done < n);
+  out_rgba[p] = make_float4(cr, cg, cb, ca);
+  out_depth[p] = znear;
 }
 
-template <int KMAX>
-static void launch_deep_k(const CompTable* tab, int k, int n_pixels, float4* out_rgba, float* out_depth,
-                          int cu_count, hipStream_t st) {
-  const int tiles = (n_pixels + 63) / 64;
-  const int grid = std::max(1, std::min(tiles, cu_count * 8));
-  hipLaunchKernelGGL(composite_deep_kernel<KMAX>, dim3(grid), dim3(64), 0, st, tab, k, n_pixels, out_rgba,
-                     out_depth);
-}
-
-hipError_t launch_composite_deep(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
-                                 int cu_count, hipStream_t st) {
+hipError_t launch_composite_deep(const CompTable* table_dev, int parts, int n_pixels, float4* out_rgba,
+                                 float* out_depth, hipStream_t st) {
   if (n_pixels <= 0) return hipSuccess;
-  if (k <= 16)
-    launch_deep_k<16>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
-  else if (k <= 64)
-    launch_deep_k<64>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
-  else if (k <= 128)
-    launch_deep_k<128>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
-  else
-    launch_deep_k<256>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
+  hipLaunchKernelGGL(deep_merge_kernel, dim3((n_pixels + 255) / 256), dim3(256), 0, st, table_dev, parts, n_pixels,
+                     out_rgba, out_depth);
   return hipGetLastError();
 }
 

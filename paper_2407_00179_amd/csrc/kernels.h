@@ -37,20 +37,18 @@ struct CompTable {
   const float4* rgba[kMaxFrags];
   const float* depth[kMaxFrags];
   int idrank[kMaxFrags];
-  // deep-frame layers: source k is layer `layer[k]` of a frame whose per-pixel
-  // fragment counts are count[k] (live where layer < count); null for flat frames
+  // deep frames: per-pixel fragment counts of part k (null for flat frames)
   const int* count[kMaxFrags];
-  int layer[kMaxFrags];
 };
 // fix_count / fix_list: device scratch for pixels whose fragments break the tile
 // order (fix_count: two ints, zero on entry and left zero on exit; fix_list holds
 // n_pixels ints); prior: kCompPriorFloats floats of scratch for the sampled nearest
 // depth per source; cu_count: compute units of the device (sizes the grids).
 constexpr int kCompPriorFloats = kMaxFrags * 8;
-// Merge deep-frame layers (every source carries count/layer) with the per-wave
-// general compositor.
-hipError_t launch_composite_deep(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
-                                 int cu_count, hipStream_t st);
+// Merge of deep frames: entry r of the table is part r (layer-major rgba/depth
+// bases, counts, idrank = its place in rank order); parts <= kMaxFrags.
+hipError_t launch_composite_deep(const CompTable* table_dev, int parts, int n_pixels, float4* out_rgba,
+                                 float* out_depth, hipStream_t st);
 hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
                             int* fix_count, int* fix_list, float* prior, int cu_count, hipStream_t st);
 

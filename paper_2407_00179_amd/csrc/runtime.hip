@@ -175,17 +175,15 @@ dpr_status ensure_majorants(dpr_world_t* w) {
 // Composite tables are cached per (frames, ids) so repeated composites of the same
 // frames (every dpr_render_frame) issue no host-to-device traffic at all.
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
-                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts,
-                      const std::vector<int>* layers) {
+                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts) {
   const size_t k = rgba.size();
   std::vector<uint64_t> key;
-  key.reserve(5 * k);
+  key.reserve(4 * k);
   for (size_t i = 0; i < k; ++i) {
     key.push_back((uint64_t)(uintptr_t)rgba[i]);
     key.push_back((uint64_t)(uintptr_t)depth[i]);
     key.push_back((uint64_t)(uint32_t)ids[i]);
     key.push_back(counts ? (uint64_t)(uintptr_t)(*counts)[i] : 0);
-    key.push_back(layers ? (uint64_t)(uint32_t)(*layers)[i] : 0);
   }
   auto it = dev->comp_cache.find(key);
   if (it != dev->comp_cache.end()) {
@@ -213,7 +211,6 @@ dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, co
     e.host->rgba[i] = rgba[i];
     e.host->depth[i] = depth[i];
     e.host->count[i] = counts ? (*counts)[i] : nullptr;
-    e.host->layer[i] = layers ? (*layers)[i] : 0;
   }
   dpr_status st = dev_alloc((void**)&e.dev, sizeof(CompTable), "composite table");
   if (st != DPR_OK) {
@@ -803,12 +800,11 @@ dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32
   if (!dev || !parts || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: NULL argument");
   if (k < 1) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: k = %d", k);
   if (out->dev != dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: out belongs to another device");
+  if (k > kMaxFrags) return fail(DPR_ERR_UNSUPPORTED, "dpr_composite_deep: %d parts > %d", k, kMaxFrags);
   std::vector<const float4*> rg;
   std::vector<const float*> dp;
-  std::vector<int32_t> id;
+  std::vector<int32_t> ranks;
   std::vector<const int*> cnt;
-  std::vector<int> lay, ranks;
-  const size_t P = (size_t)out->w * out->h;
   for (int j = 0; j < k; ++j) {
     const dpr_deep_frame f = parts[j];
     if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: part %d is NULL", j);
@@ -819,28 +815,22 @@ dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32
                   out->w, out->h);
     if (f->rank < 0)
       return fail(DPR_ERR_INVALID_STATE, "dpr_composite_deep: part %d was not rendered by dpr_render_deep", j);
-    if ((int)rg.size() + f->cap > kMaxFrags)
-      return fail(DPR_ERR_UNSUPPORTED, "dpr_composite_deep: capacities sum to more than %d", kMaxFrags);
+    rg.push_back(f->rgba);
+    dp.push_back(f->depth);
     ranks.push_back(f->rank);
-    // source (part, layer).  Ties in depth must order as the fragments' ids: inside
-    // a part the layers are already in (depth, id) order, and ids of different
-    // parts differ in their rank, so ranking the sources by (rank, layer) does it
-    for (int l = 0; l < f->cap; ++l) {
-      rg.push_back(f->rgba + (size_t)l * P);
-      dp.push_back(f->depth + (size_t)l * P);
-      id.push_back(f->rank * 256 + l);
-      cnt.push_back(f->counts);
-      lay.push_back(l);
-    }
+    cnt.push_back(f->counts);
   }
-  std::vector<int> sr = ranks;
+  // Ties in depth order as the fragments' ids: inside a part the layers are in
+  // (depth, id) order, and ids of different parts differ in their rank, so the
+  // kernel ranks fragments by (depth, part rank, layer)
+  std::vector<int32_t> sr = ranks;
   std::sort(sr.begin(), sr.end());
   if (std::adjacent_find(sr.begin(), sr.end()) != sr.end())
     return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: the parts must come from distinct ranks");
   CompTable* tab = nullptr;
-  dpr_status st = comp_table(dev, rg, dp, id, &tab, &cnt, &lay);
+  dpr_status st = comp_table(dev, rg, dp, ranks, &tab, &cnt);
   if (st != DPR_OK) return st;
-  DPR_HIP(launch_composite_deep(tab, (int)rg.size(), (int)P, (float4*)out->rgba, out->depth, dev->cu_count,
+  DPR_HIP(launch_composite_deep(tab, k, (int)((size_t)out->w * out->h), (float4*)out->rgba, out->depth,
                                 dev->stream));
   return DPR_OK;
 }

@@ -135,7 +135,6 @@ dpr_status ensure_majorants(dpr_world_t* w);
 dpr_status render_frame_batched(dpr_world w, dpr_frame out);
 dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out);
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
-                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts = nullptr,
-                      const std::vector<int>* layers = nullptr);
+                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts = nullptr);
 
 }  // namespace dpr

@@ -134,6 +134,47 @@ def test_interleaved_partition_deep_composite(gpu_lib, dpr):
         h.release()
 
 
+def test_deep_composite_more_fragments_than_one_pass(gpu_lib, dpr):
+    """12 slabs across the view direction dealt alternately to 2 ranks: pixels
+    hold up to 12 fragments, so the merge takes more than one selection pass."""
+    dims = (48, 20, 20)
+    vol = _volume(dims, 71)
+    tf = make_tf(2003)
+    prm = RenderParams(0.5, 1.0, 12.0)
+    cam = orbit_camera(dims, 128, 96, az_deg=8.0, el_deg=5.0)
+    boxes = even_split(dims, (12, 1, 1))
+    deeps, worlds = [], []
+    for r in range(2):
+        mine = boxes[r::2]
+        w = make_world(dpr, gpu_lib, vol, dims, mine, tf, prm, cam, mc=4)
+        d = dpr.DeepFrame(gpu_lib, cam.width, cam.height, len(mine))
+        w.render_deep(5 - 3 * r, d)
+        deeps.append(d)
+        worlds.append(w)
+    total = sum(_deep_np(d)[0] for d in deeps)
+    log(f"fragments per pixel: max {total.max()}, pixels above 8: {(total > 8).sum()}")
+    assert (total > 8).sum() >= 100
+    out = dpr.Frame(gpu_lib, cam.width, cam.height)
+    dpr.composite_deep(gpu_lib, deeps, out)
+    got, gz, _ = frame_np(out)
+    px, py = np.meshgrid(np.arange(cam.width), np.arange(cam.height))
+    full, fz, _ = oracle.render_image(vol, dims, tf, prm, cam, px.ravel(), py.ravel())
+    err = np.max(np.abs(got - full))
+    log(f"12-slab deep composite vs unsplit oracle: {err:.3e}")
+    assert err <= TOL_F32
+    hit = np.isfinite(fz)
+    assert np.array_equal(np.isfinite(gz), hit) and np.max(np.abs(gz[hit] - fz[hit])) <= 1e-5
+    # the oracle's merge of the GPU's own deep frames, element by element
+    parts = [(c, r_, z_, f_) for c, r_, z_, f_ in (_deep_np(d) for d in deeps)]
+    want, wz = oracle.composite_deep(parts)
+    assert np.max(np.abs(got - want)) <= TOL_F32 and np.array_equal(gz[hit], wz[hit])
+    o2 = dpr.Frame(gpu_lib, cam.width, cam.height)
+    dpr.composite_deep(gpu_lib, deeps[::-1], o2)
+    assert np.array_equal(frame_np(o2)[0], got)
+    for h in deeps + worlds + [out, o2]:
+        h.release()
+
+
 def test_deep_argument_errors(gpu_lib, dpr):
     dims = (24, 20, 16)
     vol = _volume(dims, 3)
