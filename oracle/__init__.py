@@ -22,6 +22,10 @@ What it computes, and where the paper fixes it:
 * Gradients of an L2 image loss with respect to the density grid and the
   transfer-function table.  ``grad.py``.
 * An independent loop-based brute-force renderer for tiny inputs.  ``brute.py``.
+* Iso-surface fragments: an opaque, shaded iso-surface of the trilinear field
+  found on the same sample lattice and mixed with the emission-absorption march
+  (the paper renders iso-surfaces through the same pipeline: Fig. 1c, Fig. 3c,
+  Fig. 4).  ``iso.py``.
 * Deep (multi-fragment) partial frames of ranks with non-convex data and their
   per-pixel merge (section 5.1.1 allows several fragments per pixel; section 2.1
   and Fig. 6 on non-convex partitions).  ``deep.py``.
@@ -29,7 +33,9 @@ What it computes, and where the paper fixes it:
 Pins (tests marked ``not gpu``): closed-form transmittance of a constant volume,
 O(dt^2) convergence to the analytic integral of an affine field, brute force on
 tiny grids, the split invariant (one brick == k bricks with ghosts, composited),
-composite closed forms and permutation invariance, deep frames of interleaved
+composite closed forms and permutation invariance, iso-surface closed forms on
+trilinear-exact fields, second-order convergence of the hit point, the split
+invariant with the surface, deep frames of interleaved
 (non-convex) partitions reproducing the unsplit image, numpy min/max for macrocell
 ranges, finite differences and torch.autograd (FP64) for gradients.
 """
@@ -40,5 +46,6 @@ from .render import (  # noqa: F401
 )
 from .composite import composite  # noqa: F401
 from .deep import FID_RANK, composite_deep, deep_frame  # noqa: F401
+from .iso import IsoParams, iso_classes, march_rays_iso, render_brick_iso, render_image_iso, trilinear_grad  # noqa: F401
 from .macrocell import macrocell_ranges, majorants, macrocell_grid  # noqa: F401
 from .grad import loss_and_grad, forward_image  # noqa: F401
