@@ -101,6 +101,10 @@ const char* dpr_version(void);
 dpr_status dpr_device_create(int hip_device, void* hip_stream, dpr_device* out);
 dpr_status dpr_device_set_stream(dpr_device, void* hip_stream);
 dpr_status dpr_device_sync(dpr_device);
+/* Worlds, frames and deep frames hold a reference to their device: a released
+ * device handle must not be used again, but its memory and stream binding stay
+ * valid until the last world or frame created on it is released too.  The
+ * library is not thread-safe: calls on one device come from one thread.         */
 void dpr_device_release(dpr_device);
 /* number of compute units and the wavefront size of the bound GPU */
 dpr_status dpr_device_info(dpr_device, int32_t* cu_count, int32_t* wave_size);
@@ -138,6 +142,21 @@ dpr_status dpr_world_commit(dpr_world);
  * 2 <= n_entries <= 1024, value_hi > value_lo, density_scale >= 0.              */
 dpr_status dpr_set_transfer_function(dpr_world, const float* rgba, int32_t n_entries, float value_lo,
                                      float value_hi, float density_scale);
+/* Opaque iso-surface of the world's field, rendered together with the volume.
+ * The paper draws iso-surfaces through the same data-parallel pipeline as volumes
+ * (Fig. 1c, Fig. 3c, Fig. 4); section 5.1.2 asks the local render only for colour
+ * and depth.  Along a ray, the sides (v >= value) of consecutive lattice samples
+ * are compared at every lattice point in a brick's [t_in, t_out), so each pair is
+ * tested by exactly one brick; at the first change of side the ray ends on an
+ * opaque surface at the linearly interpolated crossing, lit by a headlight:
+ * colour = TF colour at `value` * (ambient + diffuse * |cos|), cos between the
+ * ray and the gradient of the trilinear patch there (taken as 1 where the
+ * gradient is 0).  The segments before the crossing pair integrate as usual; the
+ * fragment's alpha is then 1 and its depth stays the brick entry, so bricks
+ * composite unchanged and a split volume gives the unsplit image.  enable = 0
+ * turns it off (the other arguments are then ignored).  value must be finite,
+ * ambient and diffuse >= 0.  Applies to every later render of the world.        */
+dpr_status dpr_set_isosurface(dpr_world, int32_t enable, float value, float ambient, float diffuse);
 /* Global camera (section 3.1.1: identical for every brick).                     */
 dpr_status dpr_set_camera(dpr_world, const dpr_camera*);
 dpr_status dpr_set_render_params(dpr_world, const dpr_render_params*);

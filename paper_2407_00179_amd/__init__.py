@@ -8,7 +8,9 @@ streams, nothing else.
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -24,6 +26,23 @@ __all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_
 def _torch():
     import torch
     return torch
+
+
+# objects still holding library handles; released at interpreter exit, children
+# before their device, so no release runs while modules are being torn down
+_live = weakref.WeakSet()
+
+
+def _release_all():
+    for kind in (DeepFrame, Frame, World, Device):
+        for o in [o for o in list(_live) if isinstance(o, kind)]:
+            try:
+                o.release()
+            except Exception:
+                pass
+
+
+atexit.register(_release_all)
 
 
 @dataclass
@@ -56,6 +75,7 @@ class Device:
         h = C.c_void_p()
         check(lib.dpr_device_create(index, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
+        _live.add(self)
 
     def set_stream(self, stream):
         self.stream = stream
@@ -94,6 +114,7 @@ class Frame:
         check(lib.dpr_frame_wrap(dev.h, self.width, self.height, C.c_void_p(rgba.data_ptr()),
                                  C.c_void_p(depth.data_ptr()), C.byref(h)))
         self.h = h
+        _live.add(self)
         self.counts = None
         if counts:
             self.attach_counts()
@@ -139,6 +160,7 @@ class DeepFrame:
                                       C.c_void_p(self.depth.data_ptr()), C.c_void_p(self.ids.data_ptr()),
                                       C.byref(h)))
         self.h = h
+        _live.add(self)
 
     def release(self):
         if self.h:
@@ -181,6 +203,7 @@ class World:
         h = C.c_void_p()
         check(lib.dpr_world_create(dev.h, N.I64x3(*self.dims), C.byref(h)))
         self.h = h
+        _live.add(self)
         self.params = Params()
 
     def add_brick(self, voxels, lo, hi, ghost_lo=(0, 0, 0), ghost_hi=(0, 0, 0)):
@@ -197,6 +220,13 @@ class World:
     def set_transfer_function(self, tf, lo=0.0, hi=1.0, density=20.0):
         t = np.ascontiguousarray(tf, dtype=np.float32)
         check(lib.dpr_set_transfer_function(self.h, C.c_void_p(t.ctypes.data), t.shape[0], lo, hi, density))
+
+    def set_isosurface(self, value=None, ambient=0.25, diffuse=0.75):
+        """Opaque iso-surface at ``value`` (None: off), lit by a headlight."""
+        if value is None:
+            check(lib.dpr_set_isosurface(self.h, 0, 0.0, 0.0, 0.0))
+        else:
+            check(lib.dpr_set_isosurface(self.h, 1, float(value), float(ambient), float(diffuse)))
 
     def set_camera(self, cam):
         c = to_c_camera(cam)

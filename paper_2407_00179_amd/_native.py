@@ -16,6 +16,12 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_00179_amd.build` "
                       "(the HIP library is required; there is no CPU fallback)")
 
+# torch ships its own HIP runtime under the same soname as the system one the
+# library is linked against; whichever loads first serves the whole process.
+# Loading torch first keeps one runtime, torch's, for both (the other order
+# leaves torch on a runtime it was not built with, and no device is found).
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 OK = 0
@@ -62,6 +68,7 @@ _SIGS = {
     "dpr_world_brick_count": ([P, C.POINTER(C.c_int32)], C.c_int),
     "dpr_world_brick_macrocells": ([P, C.c_int32, I32x3, P, P, C.c_size_t], C.c_int),
     "dpr_set_transfer_function": ([P, P, C.c_int32, C.c_float, C.c_float, C.c_float], C.c_int),
+    "dpr_set_isosurface": ([P, C.c_int32, C.c_float, C.c_float, C.c_float], C.c_int),
     "dpr_set_camera": ([P, C.POINTER(Camera)], C.c_int),
     "dpr_set_render_params": ([P, C.POINTER(RenderParams)], C.c_int),
     "dpr_frame_create": ([P, C.c_int32, C.c_int32, C.POINTER(P)], C.c_int),

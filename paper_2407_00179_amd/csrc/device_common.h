@@ -39,6 +39,9 @@ struct SceneG {
   double h, inv_h, dt;
   float dt_f, density, ert, tf_lo, tf_scale;  // tf_scale = (N-1)/(hi-lo)
   int ntf;
+  // opaque iso-surface (iso_on): value, ambient and diffuse weights
+  int iso_on;
+  float iso, iso_ka, iso_kd;
 };
 
 __device__ __forceinline__ uint32_t blk_x(int i) { return ((uint32_t)(i >> 3) << 9) + (uint32_t)(i & 7); }

@@ -44,7 +44,7 @@ constexpr int kRefillLanes = 32;
 
 __global__ void reset_head_kernel(int* head) { *head = 0; }
 
-template <typename T, bool SKIP, bool WIDE>
+template <typename T, bool SKIP, bool WIDE, bool ISO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void batch_march_kernel(SceneG sc, BatchG bg, const float4* __restrict__ tf) {
   extern __shared__ float4 tf_lds[];
   float4* tfb = tf_lds;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
         if (px < cam.W && py < cam.H) {
           double d[3];
           camera_ray(cam, px, py, d);
-          hit = ray_begin(sc, bg.bricks[cur_brick], cam.eye, d, r);
+          hit = ray_start<T, WIDE, ISO>(sc, bg.bricks[cur_brick], cam.eye, d, r);
         }
         if (hit) {
           active = true;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
       // early return for a refill (fewer than half the lanes marching), only while
       // a refill can take rays
       const int min_lanes = (!exhausted && pending < 0) ? kRefillLanes : 0;
-      if (ray_advance<T, SKIP, WIDE>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk, min_lanes)) {
+      if (ray_advance<T, SKIP, WIDE, ISO>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk, min_lanes)) {
         bg.frag_rgba[slot] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
         bg.frag_depth[slot] = (float)r.t_in;
         active = false;
@@ -264,7 +264,7 @@ struct BatchState {
   float* frag_depth = nullptr;
   int* head = nullptr;
   int n_items = 0, n_tiles = 0, max_k = 0;
-  int grid = 0;
+  int grid[2] = {0, 0};  // persistent grid of the march kernel without / with iso-surface
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -371,14 +371,20 @@ static dpr_status upload(V** dst, const std::vector<V>& src, hipStream_t st, con
   return DPR_OK;
 }
 
-template <typename T, bool SKIP>
+template <typename T, bool SKIP, bool ISO>
 static const void* march_fn_t(bool wide) {
-  return wide ? (const void*)batch_march_kernel<T, SKIP, true> : (const void*)batch_march_kernel<T, SKIP, false>;
+  return wide ? (const void*)batch_march_kernel<T, SKIP, true, ISO>
+              : (const void*)batch_march_kernel<T, SKIP, false, ISO>;
 }
 
-static const void* march_fn(bool f16, bool skip, bool wide) {
-  if (f16) return skip ? march_fn_t<__half, true>(wide) : march_fn_t<__half, false>(wide);
-  return skip ? march_fn_t<float, true>(wide) : march_fn_t<float, false>(wide);
+template <typename T, bool SKIP>
+static const void* march_fn_s(bool wide, bool iso) {
+  return iso ? march_fn_t<T, SKIP, true>(wide) : march_fn_t<T, SKIP, false>(wide);
+}
+
+static const void* march_fn(bool f16, bool skip, bool wide, bool iso) {
+  if (f16) return skip ? march_fn_s<__half, true>(wide, iso) : march_fn_s<__half, false>(wide, iso);
+  return skip ? march_fn_s<float, true>(wide, iso) : march_fn_s<float, false>(wide, iso);
 }
 
 static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool timed) {
@@ -397,9 +403,10 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, b->head);
   if (timed) (void)hipEventRecord(b->ev[0], st);
-  const void* fn = march_fn(f16, b->skip, b->wide());
+  const int iso = sc.iso_on ? 1 : 0;
+  const void* fn = march_fn(f16, b->skip, b->wide(), iso);
   void* args[] = {(void*)&sc, (void*)&g, (void*)&w->tf_dev};
-  const hipError_t le = hipLaunchKernel(fn, dim3(b->grid), dim3(256), args, lds, st);
+  const hipError_t le = hipLaunchKernel(fn, dim3(b->grid[iso]), dim3(256), args, lds, st);
   if (le != hipSuccess) return le;
   if (timed) (void)hipEventRecord(b->ev[1], st);
   const int tp = b->tile_w * b->tile_h;
@@ -533,13 +540,15 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   for (auto& e : b->ev)
     if (!e) DPR_HIP(hipEventCreate(&e));
   // persistent grid: as many 256-thread workgroups as fit on the GPU at once
-  int per_cu = 0;
   const bool f16 = w->bricks[0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
-  hipError_t e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, march_fn(f16, b->skip, b->wide()), 256, lds);
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
-  b->grid = w->dev->cu_count * per_cu;
+  for (int iso = 0; iso < 2; ++iso) {
+    int per_cu = 0;
+    const hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, march_fn(f16, b->skip, b->wide(), iso), 256, lds);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    b->grid[iso] = w->dev->cu_count * per_cu;
+  }
   return DPR_OK;
 }
 

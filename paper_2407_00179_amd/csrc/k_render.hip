@@ -1,6 +1,7 @@
 // Brick ingest (8^3 relayout), macrocell ranges, transfer-function majorants and
 // the per-brick emission-absorption ray march, for gfx950.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "device_common.h"
@@ -176,13 +177,24 @@ __global__ __launch_bounds__(256) void majorant_kernel(MajJobs jobs, const float
   int e1 = min((int)ceilf(xb) + 1, ntf - 1);
   float a = 0.f;
   for (int e = e0; e <= e1; ++e) a = fmaxf(a, alpha[e]);
+  if (jobs.iso_on && a == 0.f) {
+    // a margin of 1e-6 of the range's magnitude covers the rounding of FP32
+    // trilinear values (a few ulps); no contraction, so the class is exact
+    const float mg = __fmul_rn(1e-6f, fmaxf(fabsf(r.x), fabsf(r.y)));
+    if (r.y < __fsub_rn(jobs.iso, mg))
+      a = 0.f;
+    else if (r.x > __fadd_rn(jobs.iso, mg))
+      a = -1.f;
+    else
+      a = 1.f;
+  }
   jobs.maj[j][m] = a;
 }
 
 // Plain per-brick launch: one thread per pixel, 16x16 tiles as four 8x8 waves,
 // tiles assigned so that each XCD (round-robin workgroup dispatch) walks one
 // contiguous band of the screen and keeps its part of the brick in its own L2.
-template <typename T, bool SKIP, bool WIDE>
+template <typename T, bool SKIP, bool WIDE, bool ISO>
 __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG cam, const float4* __restrict__ tf,
                                                     float4* __restrict__ out_rgba, float* __restrict__ out_depth,
                                                     int* __restrict__ out_count, int tiles_x, int n_tiles) {
@@ -204,8 +216,8 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
   camera_ray(cam, px, py, d);
   RayState r;
   const size_t p = (size_t)py * cam.W + px;
-  if (ray_begin(sc, b, cam.eye, d, r)) {
-    ray_advance<T, SKIP, WIDE>(sc, b, tfb, tfs, r, 0x7fffffff);
+  if (ray_start<T, WIDE, ISO>(sc, b, cam.eye, d, r)) {
+    ray_advance<T, SKIP, WIDE, ISO>(sc, b, tfb, tfs, r, 0x7fffffff);
     out_rgba[p] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
     out_depth[p] = (float)r.t_in;
   } else {
@@ -309,17 +321,19 @@ hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, cons
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, grid, block, lds, st, sc, b, cam, tf, rgba, depth, count, tx, n_tiles);
   };
-  if (f16) {
-    if (skip)
-      b.wide ? go(march_kernel<__half, true, true>) : go(march_kernel<__half, true, false>);
-    else
-      b.wide ? go(march_kernel<__half, false, true>) : go(march_kernel<__half, false, false>);
-  } else {
-    if (skip)
-      b.wide ? go(march_kernel<float, true, true>) : go(march_kernel<float, true, false>);
-    else
-      b.wide ? go(march_kernel<float, false, true>) : go(march_kernel<float, false, false>);
-  }
+  auto by_wide = [&](auto t, auto sk, auto iso) {
+    using T = decltype(t);
+    constexpr bool S = decltype(sk)::value, I = decltype(iso)::value;
+    b.wide ? go(march_kernel<T, S, true, I>) : go(march_kernel<T, S, false, I>);
+  };
+  auto by_iso = [&](auto t, auto sk) {
+    sc.iso_on ? by_wide(t, sk, std::true_type{}) : by_wide(t, sk, std::false_type{});
+  };
+  auto by_skip = [&](auto t) { skip ? by_iso(t, std::true_type{}) : by_iso(t, std::false_type{}); };
+  if (f16)
+    by_skip(__half{});
+  else
+    by_skip(float{});
   return hipGetLastError();
 }
 

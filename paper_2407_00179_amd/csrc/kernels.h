@@ -25,6 +25,10 @@ struct MajJobs {
   float* maj[kMajJobs];
   int count[kMajJobs];
   int n;
+  // with an iso-surface, a macrocell of majorant 0 gets its skip class: 0 (every
+  // sample below iso), -1 (every sample at or above), 1 (must be sampled)
+  int iso_on;
+  float iso;
 };
 hipError_t launch_majorants(const MajJobs& jobs, const float4* tf, int ntf, float lo, float hi, hipStream_t st);
 hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, const float4* tf, bool f16, bool skip,

@@ -9,6 +9,14 @@
 // segment with no per-sample macrocell logic.  Voxel gathers of the next sample
 // are issued before the current sample is shaded.  For bricks below 4 GiB a voxel
 // address is a 32-bit byte offset from the brick base.
+//
+// Iso-surfaces (ISO): the sides (v >= v_iso) of consecutive samples are compared
+// at every lattice point the brick owns (those in [t_in, t_out)); the first change
+// of side is an opaque surface, lit at the linearly interpolated crossing with the
+// gradient of the trilinear patch there, and closes the ray.  A macrocell is then
+// skipped only when its majorant is 0, its value range lies on one side of v_iso,
+// and that side is the previous sample's (classes encoded in the majorant: 0 below,
+// -1 at or above, positive: sample it).
 #pragma once
 
 #include "device_common.h"
@@ -27,7 +35,12 @@ struct RayState {
   int n;                 // logical samples processed
   float dl_first, dl_last;  // D * clipped length of the first / last segment
   float T, cr, cg, cb;   // transmittance and premultiplied colour
+  float pv;              // iso-surfaces: value of the previous sample
+  int pst;               // iso-surfaces: bit 0 side of the previous sample, bit 1 the next
+                         // sample closes a tested pair, bit 2 pv holds the value
 };
+
+constexpr int kIsoSide = 1, kIsoPair = 2, kIsoKnown = 4;
 
 // Clip the ray against the brick's owned box and set up its march.  Returns false
 // on a miss (zero-length chords included).
@@ -151,15 +164,18 @@ __device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const 
   }
 }
 
-// Shade one sample; returns true when the ray terminates early.
 template <typename T>
-__device__ __forceinline__ bool shade(const SceneG& sc, const float4* __restrict__ tfb,
-                                      const float4* __restrict__ tfs, const Gather<T>& g, float Dl, double& tau_acc,
-                                      float& tr, float& cr, float& cg, float& cb) {
+__device__ __forceinline__ float trilerp(const Gather<T>& g) {
   const float c00 = fmaf(g.fx, g.v[1] - g.v[0], g.v[0]), c01 = fmaf(g.fx, g.v[3] - g.v[2], g.v[2]);
   const float c10 = fmaf(g.fx, g.v[5] - g.v[4], g.v[4]), c11 = fmaf(g.fx, g.v[7] - g.v[6], g.v[6]);
   const float c0 = fmaf(g.fy, c01 - c00, c00), c1 = fmaf(g.fy, c11 - c10, c10);
-  const float v = fmaf(g.fz, c1 - c0, c0);
+  return fmaf(g.fz, c1 - c0, c0);
+}
+
+// Shade one sample of value v; returns true when the ray terminates early.
+__device__ __forceinline__ bool shade_v(const SceneG& sc, const float4* __restrict__ tfb,
+                                        const float4* __restrict__ tfs, float v, float Dl, double& tau_acc,
+                                        float& tr, float& cr, float& cg, float& cb) {
   float x = (v - sc.tf_lo) * sc.tf_scale;
   x = fminf(fmaxf(x, 0.f), (float)(sc.ntf - 1));
   const int j = min((int)x, sc.ntf - 2);
@@ -180,10 +196,90 @@ __device__ __forceinline__ bool shade(const SceneG& sc, const float4* __restrict
   return false;
 }
 
+template <typename T>
+__device__ __forceinline__ bool shade(const SceneG& sc, const float4* __restrict__ tfb,
+                                      const float4* __restrict__ tfs, const Gather<T>& g, float Dl, double& tau_acc,
+                                      float& tr, float& cr, float& cg, float& cb) {
+  return shade_v(sc, tfb, tfs, trilerp(g), Dl, tau_acc, tr, cr, cg, cb);
+}
+
+// Set up the ray (ray_begin) and, for iso-surfaces, the pair at the brick entry:
+// when the first processed segment starts exactly at t_in its lattice point is
+// this brick's, and the sample half a step before the entry opens the pair.
+template <typename T, bool WIDE, bool ISO>
+__device__ __forceinline__ bool ray_start(const SceneG& sc, const BrickG& b, const double o[3], const double d[3],
+                                          RayState& r) {
+  if (!ray_begin(sc, b, o, d, r)) return false;
+  if constexpr (ISO) {
+    r.pv = 0.f;
+    r.pst = 0;
+    if ((double)r.s0 * sc.dt >= r.t_in) {
+      const int64_t q[3] = {r.p[0] - r.dp[0], r.p[1] - r.dp[1], r.p[2] - r.dp[2]};
+      Gather<T> g;
+      gather<T, WIDE>(sc, b, q, g);
+      r.pv = trilerp(g);
+      r.pst = kIsoPair | kIsoKnown | (r.pv >= sc.iso ? kIsoSide : 0);
+    }
+  }
+  return true;
+}
+
+// The opaque surface between samples s - 1 and s (value vs; q: the fixed-point
+// point of sample s): crossing by linear interpolation, normal = gradient of the
+// trilinear patch there, colour = TF colour at v_iso * (k_a + k_d |cos|).
+template <typename T, bool WIDE>
+__device__ __forceinline__ void iso_hit(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
+                                     const float4* __restrict__ tfs, const int64_t q[3], const int64_t dq[3],
+                                     float vs, int pst, float pv, float& tr, float& cr, float& cg, float& cb) {
+  const int64_t qp[3] = {q[0] - dq[0], q[1] - dq[1], q[2] - dq[2]};
+  float vp = pv;
+  if (!(pst & kIsoKnown)) {  // the previous sample was skipped: its value now
+    Gather<T> g;
+    gather<T, WIDE>(sc, b, qp, g);
+    vp = trilerp(g);
+  }
+  const float f = (sc.iso - vp) / (vs - vp);
+  int64_t qh[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) qh[a] = qp[a] + __double2ll_rn((double)f * (double)dq[a]);
+  Gather<T> g;
+  gather<T, WIDE>(sc, b, qh, g);
+  const float* v = g.v;
+  // d/dx, d/dy, d/dz of the patch: the edge differences, interpolated in the other two axes
+  const float x0 = fmaf(g.fy, (v[3] - v[2]) - (v[1] - v[0]), v[1] - v[0]);
+  const float x1 = fmaf(g.fy, (v[7] - v[6]) - (v[5] - v[4]), v[5] - v[4]);
+  const float gx = fmaf(g.fz, x1 - x0, x0);
+  const float y0 = fmaf(g.fx, (v[3] - v[1]) - (v[2] - v[0]), v[2] - v[0]);
+  const float y1 = fmaf(g.fx, (v[7] - v[5]) - (v[6] - v[4]), v[6] - v[4]);
+  const float gy = fmaf(g.fz, y1 - y0, y0);
+  const float z0 = fmaf(g.fx, (v[5] - v[1]) - (v[4] - v[0]), v[4] - v[0]);
+  const float z1 = fmaf(g.fx, (v[7] - v[3]) - (v[6] - v[2]), v[6] - v[2]);
+  const float gz = fmaf(g.fy, z1 - z0, z0);
+  // the ray direction is parallel to the per-segment advance.  Every product and
+  // sum is spelled out (fmaf, __fmul_rn): left to contraction, the compiler may
+  // associate these sums differently in different kernels, and the skip and
+  // no-skip marches would then differ in the last bit
+  const float dx = (float)dq[0], dy = (float)dq[1], dz = (float)dq[2];
+  const float nn = fmaf(gz, gz, fmaf(gy, gy, __fmul_rn(gx, gx)));
+  const float dd = fmaf(dz, dz, fmaf(dy, dy, __fmul_rn(dx, dx)));
+  const float dot = fmaf(gz, dz, fmaf(gy, dy, __fmul_rn(gx, dx)));
+  const float cosv = nn > 0.f ? fabsf(dot) / sqrtf(__fmul_rn(nn, dd)) : 1.f;
+  float x = (sc.iso - sc.tf_lo) * sc.tf_scale;
+  x = fminf(fmaxf(x, 0.f), (float)(sc.ntf - 1));
+  const int j = min((int)x, sc.ntf - 2);
+  const float w = x - (float)j;
+  const float4 tb = tfb[j], ts = tfs[j];
+  const float lit = fmaf(sc.iso_kd, fminf(cosv, 1.f), sc.iso_ka);
+  cr = fmaf(tr, __fmul_rn(fmaf(w, ts.x, tb.x), lit), cr);
+  cg = fmaf(tr, __fmul_rn(fmaf(w, ts.y, tb.y), lit), cg);
+  cb = fmaf(tr, __fmul_rn(fmaf(w, ts.z, tb.z), lit), cb);
+  tr = 0.f;
+}
+
 // Advance by at most `budget` lattice segments.  Returns true once the ray is
 // finished: past its last segment, or terminated early (1 - T >= ert, tested
 // after every segment that changed T).
-template <typename T, bool SKIP, bool WIDE>
+template <typename T, bool SKIP, bool WIDE, bool ISO>
 __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
                                             const float4* __restrict__ tfs, RayState& r, int budget,
                                             int min_lanes = 0) {
@@ -195,6 +291,9 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
   float tr = r.T, cr = r.cr, cg = r.cg, cb = r.cb;
   double tau_acc = r.tau;
   bool done = false;
+  int pst = ISO ? r.pst : 0;
+  float pv = ISO ? r.pv : 0.f, vh = 0.f;
+  bool hit = false;
   // ga holds the voxels of the current sample point when pre is set: a run of even
   // length ends with the next sample's gather in ga, and the next run reuses it
   Gather<T> ga, gb;
@@ -215,7 +314,13 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
         const int cell = (int)((pp[a] + half) >> 32);
         m[a] = min(max((cell - b.olo[a]) >> b.mc_shift, 0), b.mdim[a] - 1);
       }
-      empty = b.majorant[(m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]] == 0.f;
+      const float mj = b.majorant[(m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]];
+      if constexpr (ISO) {
+        empty = mj <= 0.f && (!(pst & kIsoPair) || ((mj < 0.f) == (bool)(pst & kIsoSide)));
+        if (empty) pst = kIsoPair | (mj < 0.f ? kIsoSide : 0);
+      } else {
+        empty = mj == 0.f;
+      }
       if (empty) {
         // exactly the samples left inside this empty macrocell (outer cells unbounded)
         const int64_t dd[3] = {d0, d1, d2};
@@ -256,7 +361,20 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
       const float Dl = (s == r.s0) ? r.dl_first : ((s == r.s1) ? r.dl_last : Ddt);
       ++n;
       ++s;
-      return shade<T>(sc, tfb, tfs, g, Dl, tau_acc, tr, cr, cg, cb);
+      if constexpr (ISO) {
+        const float v = trilerp(g);
+        const int side = v >= sc.iso ? kIsoSide : 0;
+        if ((pst & kIsoPair) && side != (pst & kIsoSide)) {  // the surface: no emission from this segment
+          hit = true;
+          vh = v;
+          return true;
+        }
+        pst = kIsoPair | kIsoKnown | side;
+        pv = v;
+        return shade_v(sc, tfb, tfs, v, Dl, tau_acc, tr, cr, cg, cb);
+      } else {
+        return shade<T>(sc, tfb, tfs, g, Dl, tau_acc, tr, cr, cg, cb);
+      }
     };
     if (!pre) {
       const int64_t pc[3] = {p0, p1, p2};
@@ -290,6 +408,13 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
     }
     pre = (run & 1) == 0;
   }
+  if constexpr (ISO) {
+    if (hit) {  // the hit sample is s - 1, one segment behind the current point
+      const int64_t q[3] = {p0 - d0, p1 - d1, p2 - d2};
+      const int64_t dq[3] = {d0, d1, d2};
+      iso_hit<T, WIDE>(sc, b, tfb, tfs, q, dq, vh, pst, pv, tr, cr, cg, cb);
+    }
+  }
   // the fixed-point position always corresponds to segment s
   r.s = s;
   r.p[0] = p0;
@@ -301,6 +426,10 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
   r.cb = cb;
   r.tau = tau_acc;
   r.n = n;
+  if constexpr (ISO) {
+    r.pst = pst;
+    r.pv = pv;
+  }
   return done || s > r.s1;
 }
 

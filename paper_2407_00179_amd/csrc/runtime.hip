@@ -124,6 +124,12 @@ SceneG make_scene(const dpr_world_t* w) {
   s.tf_lo = w->tf_lo;
   s.tf_scale = (float)(w->ntf - 1) / (w->tf_hi - w->tf_lo);
   s.ntf = w->ntf;
+  if (w->iso_on) {
+    s.iso_on = 1;
+    s.iso = w->iso;
+    s.iso_ka = w->iso_ka;
+    s.iso_kd = w->iso_kd;
+  }
   return s;
 }
 
@@ -150,6 +156,8 @@ BrickG Brick::device_view(bool with_majorant, bool force_wide) const {
 dpr_status ensure_majorants(dpr_world_t* w) {
   // bricks whose majorants predate the current TF, up to kMajJobs per launch
   MajJobs jobs{};
+  jobs.iso_on = w->iso_on ? 1 : 0;
+  jobs.iso = w->iso;
   Brick* pend[kMajJobs];
   auto flush = [&]() -> dpr_status {
     if (!jobs.n) return DPR_OK;
@@ -334,8 +342,10 @@ dpr_status dpr_device_info(dpr_device d, int32_t* cu, int32_t* ws) {
   return DPR_OK;
 }
 
-void dpr_device_release(dpr_device d) {
-  if (!d) return;
+static void device_retain(dpr_device d) { ++d->refs; }
+
+static void device_drop(dpr_device d) {
+  if (--d->refs > 0) return;
   (void)hipStreamSynchronize(d->stream);
   for (auto& kv : d->comp_cache) {
     dev_free(kv.second.dev);
@@ -347,6 +357,11 @@ void dpr_device_release(dpr_device d) {
   delete d;
 }
 
+void dpr_device_release(dpr_device d) {
+  if (!d) return;
+  device_drop(d);
+}
+
 // ---------------------------------------------------------------- world
 dpr_status dpr_world_create(dpr_device d, const int64_t dims[3], dpr_world* out) {
   if (!d || !dims || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_create: NULL argument");
@@ -356,6 +371,7 @@ dpr_status dpr_world_create(dpr_device d, const int64_t dims[3], dpr_world* out)
                   (long long)dims[a]);
   auto* w = new dpr_world_t;
   w->dev = d;
+  device_retain(d);
   for (int a = 0; a < 3; ++a) w->dims[a] = dims[a];
   *out = w;
   return DPR_OK;
@@ -375,7 +391,9 @@ void dpr_world_release(dpr_world w) {
   dev_free(w->tf_dev);
   if (w->tf_host) (void)hipHostFree(w->tf_host);
   if (w->tf_ev) (void)hipEventDestroy(w->tf_ev);
+  dpr_device d = w->dev;
   delete w;
+  device_drop(d);
 }
 
 dpr_status dpr_world_add_brick(dpr_world w, const void* voxels, dpr_dtype dtype, int on_device,
@@ -594,6 +612,21 @@ dpr_status dpr_set_transfer_function(dpr_world w, const float* rgba, int32_t n, 
   return DPR_OK;
 }
 
+dpr_status dpr_set_isosurface(dpr_world w, int32_t enable, float value, float ambient, float diffuse) {
+  if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_isosurface: NULL world");
+  if (enable) {
+    if (!std::isfinite(value)) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_isosurface: value %g", value);
+    if (!(ambient >= 0.f) || !std::isfinite(ambient) || !(diffuse >= 0.f) || !std::isfinite(diffuse))
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_isosurface: ambient %g, diffuse %g", ambient, diffuse);
+    w->iso = value;
+    w->iso_ka = ambient;
+    w->iso_kd = diffuse;
+  }
+  w->iso_on = enable != 0;
+  ++w->tf_version;  // the majorants carry the skip classes of the surface
+  return DPR_OK;
+}
+
 dpr_status dpr_set_camera(dpr_world w, const dpr_camera* c) {
   if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_camera: NULL world");
   dpr_status st = check_camera(c);
@@ -636,6 +669,7 @@ dpr_status dpr_frame_create(dpr_device d, int32_t wd, int32_t ht, dpr_frame* out
     delete f;
     return st;
   }
+  device_retain(d);
   *out = f;
   return DPR_OK;
 }
@@ -653,6 +687,7 @@ dpr_status dpr_frame_wrap(dpr_device d, int32_t wd, int32_t ht, float* rgba, flo
   f->rgba = rgba;
   f->depth = depth;
   f->owned = false;
+  device_retain(d);
   *out = f;
   return DPR_OK;
 }
@@ -693,7 +728,9 @@ void dpr_frame_release(dpr_frame f) {
     dev_free(f->rgba);
     dev_free(f->depth);
   }
+  dpr_device d = f->dev;
   delete f;
+  device_drop(d);
 }
 
 // ---------------------------------------------------------------- render / composite
@@ -749,6 +786,7 @@ dpr_status dpr_deep_frame_create(dpr_device d, int32_t wd, int32_t ht, int32_t c
   if (st != DPR_OK) return st;
   auto* f = new dpr_deep_frame_t;
   f->dev = d;
+  device_retain(d);  // dropped by dpr_deep_frame_release, also on the failure path below
   f->w = wd;
   f->h = ht;
   f->cap = cap;
@@ -780,6 +818,7 @@ dpr_status dpr_deep_frame_wrap(dpr_device d, int32_t wd, int32_t ht, int32_t cap
   f->rgba = (float4*)rgba;
   f->depth = depth;
   f->ids = ids;
+  device_retain(d);
   *out = f;
   return DPR_OK;
 }
@@ -793,7 +832,9 @@ void dpr_deep_frame_release(dpr_deep_frame f) {
     dev_free(f->depth);
     dev_free(f->ids);
   }
+  dpr_device d = f->dev;
   delete f;
+  device_drop(d);
 }
 
 dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32_t k, dpr_frame out) {

@@ -41,6 +41,9 @@ struct CompEntry {
 }  // namespace dpr
 
 struct dpr_device_t {
+  // references: the caller's handle plus one per live world, frame and deep frame;
+  // the device is freed when the last one is released
+  int refs = 1;
   int dev = 0;
   hipStream_t stream = nullptr;
   int cu_count = 0;
@@ -110,7 +113,10 @@ struct dpr_world_t {
   int ntf = 0;
   float tf_lo = 0.f, tf_hi = 1.f, density = 0.f;
   bool tf_set = false;
-  uint64_t tf_version = 0;
+  uint64_t tf_version = 0;  // bumped by every TF or iso-surface change (majorants are rebuilt)
+  // opaque iso-surface
+  bool iso_on = false;
+  float iso = 0.f, iso_ka = 0.25f, iso_kd = 0.75f;
   // camera and parameters
   dpr_camera cam{};
   bool cam_set = false;
