@@ -13,8 +13,9 @@ processed before termination, skipped ones included), in Msamples/s.
 
 Extra sections (same JSON line): the K=128 compositor at 3840x2160, the batched
 persistent renderer against plain per-brick launches on the 27-brick 16-camera
-workload, the backward/forward time ratio of the differentiable renderer, and deep
-(multi-fragment) frames of an interleaved 8-rank partition.
+workload, the backward/forward time ratio of the differentiable renderer, deep
+(multi-fragment) frames of an interleaved 8-rank partition, and the opaque
+iso-surface mixed with the volume.
 
 The CPU baseline (the FP64 oracle, not tuned) runs first, before any GPU use,
 on a bounded pixel sample of the default workload, over a fork pool of host cores.
@@ -376,6 +377,43 @@ def bench_deep(args, dpr, torch, dev):
                 max_abs_diff_vs_one_rank=diff)
 
 
+def bench_iso(args, dpr, torch, dev, bricks, dims, tf, cfg, cam):
+    """Opaque iso-surface at value 0.5 on the default workload (8 bricks, 1024x1024):
+    with the volume's TF (surface and volume mixed in each fragment) and with a fully
+    transparent TF (surface alone, macrocells off the surface skipped).  Each is
+    timed as a whole batched frame (march + tile composite) against the same world
+    without the surface."""
+    w = dpr.World(dev, dims)
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
+    for b in bricks:
+        w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)
+    w.commit()
+    w.set_camera(cam)
+    f = dpr.Frame(dev, cam.width, cam.height)
+    clear = np.array(tf, dtype=np.float32, copy=True)
+    clear[:, 3] = 0.0
+    reps = max(3, args.steps)
+    out = {}
+    for name, table in (("surface_and_volume", tf), ("surface_only", clear)):
+        w.set_transfer_function(table, 0.0, 1.0, cfg.density)
+        res = {}
+        for mode, iso in (("iso", 0.5), ("none", None)):
+            w.set_isosurface(iso)
+            samples = _count_samples(dpr, dev, w, [cam], len(bricks))
+            w.render_frame(f)
+            torch.cuda.synchronize()
+            ms = _timed(torch, lambda: w.render_frame(f), reps)
+            res[mode] = (samples, ms, float((f.rgba[..., 3] == 1.0).float().mean().item()))
+        (si, mi, cov), (sn, mn, _) = res["iso"], res["none"]
+        out[name] = dict(samples=si, ms_frame=mi, msamples=si / mi / 1e3, surface_pixel_fraction=cov,
+                         without_surface=dict(samples=sn, ms_frame=mn, msamples=sn / mn / 1e3))
+    f.release()
+    w.release()
+    out["workload"] = ("512^3 FP32 volume, 2x2x2 bricks, 1024x1024, step 0.5 voxel, ERT 0.99, iso value 0.5 "
+                       "(headlight, ambient 0.25, diffuse 0.75); batched frame, graph replay")
+    return out
+
+
 def bench_train(args, dpr, torch, dev):
     """256^3 FP32 density grid + 256-entry TF as parameters, 16 cameras at 512x512:
     the differentiable forward (with checkpoint stores) and the adjoint march."""
@@ -440,7 +478,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batch,cfg3,train,composite128,deep")
+    ap.add_argument("--sections", default="batch,cfg3,train,composite128,deep,iso")
     ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (scales HBM byte counters)")
@@ -536,6 +574,9 @@ def main():
     if "train" in secs:
         log("GPU: differentiable render forward/backward")
         line["train_cfg4"] = bench_train(args, dpr, torch, dev)
+    if "iso" in secs:
+        log("GPU: iso-surface on the default workload")
+        line["iso_cfg2"] = bench_iso(args, dpr, torch, dev, bricks, dims, tf, cfg, cam)
     if "deep" in secs:
         log("GPU: deep frames of an interleaved 8-rank partition")
         line["deep_8ranks"] = bench_deep(args, dpr, torch, dev)
