@@ -53,9 +53,9 @@ OPS_PER_SAMPLE = 60
 #     from a plain 256 MiB device-to-device copy in the same runs);
 #   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
 MARCH_COUNTERS = {
-    "sources_sha256": "fbd6f8e0f9e2c6853d79253023bae31f1f0a01a79d9ec3692817b4131315cdce",
-    "traffic_bytes_per_launch": 352929843,
-    "fetch_kib": 161708, "write_kib": 21296, "fetch_scale": 1.9997, "write_scale": 1.0,
+    "sources_sha256": "f0dd26a82611f86f3c3360970b7a5d02f7dd63a160aa8339eb885f64c947d825",
+    "traffic_bytes_per_launch": 350576902,
+    "fetch_kib": 160542, "write_kib": 21327, "fetch_scale": 1.9997, "write_scale": 1.0,
     "valu_lane_instr_per_sample": 61.5,
 }
 
