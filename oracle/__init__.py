@@ -26,6 +26,11 @@ What it computes, and where the paper fixes it:
   found on the same sample lattice and mixed with the emission-absorption march
   (the paper renders iso-surfaces through the same pipeline: Fig. 1c, Fig. 3c,
   Fig. 4).  ``iso.py``.
+* Data-parallel volumetric path tracing (delta tracking, next-event estimation
+  with ratio-tracked shadow rays, isotropic scattering; the rays a rank cannot
+  finish are forwarded to the rank holding the content they meet next: sections
+  2.2 and 5.2, Fig. 7), with the counter-based generator Philox4x32-10 restated
+  from its published definition.  ``path.py``, ``rng.py``.
 * Deep (multi-fragment) partial frames of ranks with non-convex data and their
   per-pixel merge (section 5.1.1 allows several fragments per pixel; section 2.1
   and Fig. 6 on non-convex partitions).  ``deep.py``.
@@ -46,6 +51,7 @@ from .render import (  # noqa: F401
 )
 from .composite import composite  # noqa: F401
 from .deep import FID_RANK, composite_deep, deep_frame  # noqa: F401
+from .path import PathParams, render_path, trace_paths  # noqa: F401
 from .iso import IsoParams, iso_classes, march_rays_iso, render_brick_iso, render_image_iso, trilinear_grad  # noqa: F401
 from .macrocell import macrocell_ranges, majorants, macrocell_grid  # noqa: F401
 from .grad import loss_and_grad, forward_image  # noqa: F401
