@@ -282,6 +282,49 @@ dpr_status dpr_render_deep(dpr_world, int32_t rank, dpr_deep_frame out);
  * on the order of `parts`.                                                     */
 dpr_status dpr_composite_deep(dpr_device, const dpr_deep_frame* parts, int32_t k, dpr_frame out);
 
+/* ---------------------------------------------------------------- path tracing */
+/* Data-parallel volumetric path tracing with ray forwarding.  The paper motivates
+ * illumination that needs rays to visit content on other ranks (section 2.2;
+ * Fig. 7, volumetric shadows) and a path tracer that forwards each ray to the
+ * rank holding the content it meets next, so every ray finds its true
+ * interactions wherever it was spawned (section 5.2; the wave-front exchange of
+ * section 2.2).  Here each brick plays one rank's part: rays advance in waves,
+ * and a ray whose next tentative collision lies in another brick is handed to
+ * that brick for the next wave.
+ * Estimator: extinction D * A(v) (the TF opacity), single-scattering albedo =
+ * the TF's RGB, isotropic phase; delta tracking under one constant majorant
+ * (D * max A over the table, so the image does not depend on the bricking);
+ * at each real collision a shadow ray towards the light estimates the
+ * transmittance by ratio tracking and adds thr * light * T / (4 pi); a path
+ * leaving the volume box adds thr * env; a path ends after max_bounces real
+ * collisions.  Random numbers: Philox4x32-10 (Salmon et al., SC 2011) with key
+ * (seed, 0x243F6A88) and counter (path id, event, 0 for the path / 1 for its
+ * shadow ray, step), uniform ((x >> 9) + 1/2) 2^-23; path id =
+ * (row * width + column) * spp + sample.  Camera rays pass through pixel
+ * centres.  Gaps between bricks are empty space.                              */
+typedef struct {
+  float light_dir[3];    /* direction the light travels (any length > 0)          */
+  float light_rgb[3];    /* radiance of the directional light, >= 0                */
+  float env_rgb[3];      /* environment radiance seen by paths leaving the box     */
+  int32_t max_bounces;   /* real collisions per path, in [1, 255]                  */
+  int32_t spp;           /* paths per pixel, >= 1                                  */
+  uint32_t seed;         /* first key word of the generator                        */
+} dpr_path_params;
+typedef struct {
+  int64_t paths;         /* camera paths traced                                    */
+  int64_t events;        /* tentative collisions of paths (real and null)          */
+  int64_t shadow_steps;  /* ratio-tracking steps of shadow rays                    */
+  int64_t forwards;      /* hand-overs of a ray to another brick                   */
+  int32_t waves;         /* waves until no ray was left                            */
+} dpr_path_stats;
+/* Render the world's camera into `out`: RGB = mean radiance of the pixel's spp
+ * paths, A = 1, depth = +inf.  out's size is the camera's.  Needs a committed
+ * world with TF and camera and one element type for all bricks.  Device memory:
+ * two ray pools of 64 B x paths x (max_bounces + 1) and 16 B x paths x
+ * (max_bounces + 1) of contributions, kept by the world for later calls.
+ * Synchronises (the host reads the size of every wave).  stats may be NULL.    */
+dpr_status dpr_render_path(dpr_world, const dpr_path_params* params, dpr_frame out, dpr_path_stats* stats);
+
 /* ---------------------------------------------------------------- training */
 /* Differentiable render of one whole volume (no bricks, ERT off) for n cameras.
  * volume: FP32 device grid of dims (x fastest); tf: n_tf RGBA FP32 (device).

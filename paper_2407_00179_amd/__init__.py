@@ -262,6 +262,17 @@ class World:
         """Every brick of this world into ``deep`` (fragment ids rank * 65536 + brick)."""
         check(lib.dpr_render_deep(self.h, int(rank), deep.h))
 
+    def render_path(self, frame: Frame, light_dir=(-0.45, -0.55, -0.7), light_rgb=(3.0, 2.8, 2.5),
+                    env_rgb=(0.15, 0.2, 0.3), max_bounces=3, spp=1, seed=1):
+        """Path-traced image of the world's camera into ``frame`` (RGB radiance, A = 1);
+        returns the tracer's counters."""
+        prm = N.PathParams((C.c_float * 3)(*light_dir), (C.c_float * 3)(*light_rgb), (C.c_float * 3)(*env_rgb),
+                           int(max_bounces), int(spp), int(seed) & 0xFFFFFFFF)
+        st = N.PathStats()
+        check(lib.dpr_render_path(self.h, C.byref(prm), frame.h, C.byref(st)))
+        return dict(paths=st.paths, events=st.events, shadow_steps=st.shadow_steps, forwards=st.forwards,
+                    waves=st.waves)
+
     def render_batch(self, cams, frames, flags=0):
         arr = (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])
         fr = (C.c_void_p * len(frames))(*[f.h.value for f in frames])

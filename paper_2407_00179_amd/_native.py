@@ -42,6 +42,16 @@ class Camera(C.Structure):
                 ("fovy_deg", C.c_double), ("width", C.c_int32), ("height", C.c_int32)]
 
 
+class PathParams(C.Structure):
+    _fields_ = [("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3), ("env_rgb", C.c_float * 3),
+                ("max_bounces", C.c_int32), ("spp", C.c_int32), ("seed", C.c_uint32)]
+
+
+class PathStats(C.Structure):
+    _fields_ = [("paths", C.c_int64), ("events", C.c_int64), ("shadow_steps", C.c_int64), ("forwards", C.c_int64),
+                ("waves", C.c_int32)]
+
+
 class RenderParams(C.Structure):
     _fields_ = [("step_voxels", C.c_float), ("ert_threshold", C.c_float), ("macrocell_cells", C.c_int32),
                 ("flags", C.c_uint32)]
@@ -90,6 +100,7 @@ _SIGS = {
     "dpr_deep_frame_release": ([P], None),
     "dpr_render_deep": ([P, C.c_int32, P], C.c_int),
     "dpr_composite_deep": ([P, P, C.c_int32, P], C.c_int),
+    "dpr_render_path": ([P, C.POINTER(PathParams), P, C.POINTER(PathStats)], C.c_int),
     "dpr_train_workspace_size": ([I64x3, P, C.c_int32, C.c_float, C.POINTER(C.c_size_t)], C.c_int),
     "dpr_render_train_forward": ([P, P, I64x3, P, C.c_int32, C.c_float, C.c_float, C.c_float,
                                   C.POINTER(RenderParams), P, C.c_int32, P, P, P, C.c_size_t], C.c_int),

@@ -1,0 +1,548 @@
+// Data-parallel volumetric path tracing with ray forwarding (dpr_render_path).
+//
+// Each brick plays one rank's part.  Rays (camera paths and their shadow rays)
+// live in a pool of 64-byte records and advance in waves: in a wave a ray is
+// worked on until it finishes, until its next tentative collision lies in
+// another brick (it is then handed to that brick for the next wave: the
+// forwarding of rays between ranks), or until a real collision (the path and the
+// shadow ray it spawns both go to the next wave).  Records are appended to the
+// next pool with one atomic per wave.  A path's contributions land in fixed
+// slots and are summed in a fixed order, so the image does not depend on the
+// order of rays in the pools, nor on the bricking: the tentative collisions come
+// from one constant majorant and a counter-based generator keyed by the path.
+//
+// Estimator (per path): delta tracking with majorant sbar = D max A; at a real
+// collision the throughput takes the albedo (TF colour), a shadow ray towards the
+// light tracks the transmittance by ratio tracking and adds thr * light * T / 4pi;
+// the path scatters isotropically until max_bounces real collisions; leaving the
+// volume box it adds thr * env.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "march.h"
+#include "runtime.hpp"
+
+namespace dpr {
+
+struct PRay {
+  float x[3];
+  float w[3];
+  float t[3];     // path: throughput; shadow: weight (throughput * light / 4 pi)
+  float a, b, c;  // pending path event: u1, u2, u3; shadow: T, length so far, length to the box exit
+  uint32_t pid;   // path id
+  uint32_t e;     // path: next event index; shadow: the event that spawned it
+  uint32_t meta;  // bit 31 shadow, bit 30 pending, bits 16..23 bounce (path) or slot (shadow),
+                  // bits 0..15 shadow step
+  int32_t brick;  // brick that works on the ray in the next wave (-1: none yet)
+};
+static_assert(sizeof(PRay) == 64, "ray records are 64 bytes");
+
+constexpr uint32_t kShadowRay = 1u << 31, kPendingEvent = 1u << 30;
+constexpr uint32_t kPathKey1 = 0x243F6A88u;
+constexpr int kStepsPerWave = 1 << 16;  // bound on one ray's steps in one wave
+constexpr int kMaxWaves = 1 << 14;
+
+struct PathG {
+  const BrickG* bricks;
+  int nbricks;
+  float sbar;
+  float box[3];
+  float l[3];   // unit direction towards the light
+  float Ll[3];  // light radiance / (4 pi)
+  float Le[3];  // environment radiance
+  int B, spp;
+  uint32_t seed;
+  int vacuum;       // sbar == 0: nothing can collide, every path sees the environment
+  float4* contrib;  // B + 1 slots per path: NEE at real collisions 0..B-1, environment at B
+  PRay* out;
+  int* out_count;
+  int out_cap;
+  unsigned long long* stats;  // events, shadow steps, forwards, pool overflows
+};
+
+// Philox4x32-10 (Salmon et al., SC 2011): ten rounds of two 32x32->64 products,
+// the key bumped by the Weyl constants before every round but the first.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// ((x >> 9) + 1/2) 2^-23: exact in FP32
+__device__ __forceinline__ float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f); }
+
+__device__ __forceinline__ float exit_dist(const PathG& pg, const float x[3], const float w[3]) {
+  float t = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (w[a] > 0.f)
+      t = fminf(t, (pg.box[a] - x[a]) / w[a]);
+    else if (w[a] < 0.f)
+      t = fminf(t, -x[a] / w[a]);
+  }
+  return t;
+}
+
+// Brick owning the cell of point q (the hint first); -1 in a gap.
+__device__ __forceinline__ int locate(const SceneG& sc, const PathG& pg, const float q[3], int hint) {
+  int c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) c[a] = min(max((int)floorf(q[a] * (float)sc.inv_h), 0), sc.dims[a] - 1);
+  auto inside = [&](int i) {
+    const BrickG& b = pg.bricks[i];
+    return c[0] >= b.olo[0] && c[0] < b.ohi[0] && c[1] >= b.olo[1] && c[1] < b.ohi[1] && c[2] >= b.olo[2] &&
+           c[2] < b.ohi[2];
+  };
+  if (hint >= 0 && inside(hint)) return hint;
+  for (int i = 0; i < pg.nbricks; ++i)
+    if (inside(i)) return i;
+  return -1;
+}
+
+// Extinction and albedo at q from brick b (trilinear sample, TF lookup).
+template <typename T, bool WIDE>
+__device__ __forceinline__ void medium(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
+                                       const float4* __restrict__ tfs, const float q[3], float& sigma,
+                                       float alb[3]) {
+  int64_t p[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p[a] = __double2ll_rn(((double)q[a] * sc.inv_h - 0.5) * kFix);
+  Gather<T> g;
+  gather<T, WIDE>(sc, b, p, g);
+  const float v = trilerp(g);
+  float x = (v - sc.tf_lo) * sc.tf_scale;
+  x = fminf(fmaxf(x, 0.f), (float)(sc.ntf - 1));
+  const int j = min((int)x, sc.ntf - 2);
+  const float w = x - (float)j;
+  const float4 tb = tfb[j], ts = tfs[j];
+  sigma = sc.density * fmaf(w, ts.w, tb.w);
+  alb[0] = fmaf(w, ts.x, tb.x);
+  alb[1] = fmaf(w, ts.y, tb.y);
+  alb[2] = fmaf(w, ts.z, tb.z);
+}
+
+__device__ __forceinline__ void add_contrib(const PathG& pg, uint32_t pid, int slot, float r, float g, float b) {
+  pg.contrib[(size_t)pid * (pg.B + 1) + slot] = make_float4(r, g, b, 0.f);
+}
+
+// Append up to two records per lane with one atomic per wave (called by every
+// lane of the wave at the same point).
+__device__ __forceinline__ void emit2(const PathG& pg, const PRay& ra, bool ha, const PRay& rb, bool hb) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t ma = __ballot(ha), mb = __ballot(hb);
+  const int na = __popcll(ma), total = na + __popcll(mb);
+  if (total == 0) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(pg.out_count, total);
+  base = __shfl(base, 0);
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int ia = base + __popcll(ma & lt), ib = base + na + __popcll(mb & lt);
+  bool over = false;
+  if (ha) {
+    if (ia < pg.out_cap) pg.out[ia] = ra;
+    else over = true;
+  }
+  if (hb) {
+    if (ib < pg.out_cap) pg.out[ib] = rb;
+    else over = true;
+  }
+  if (over) atomicAdd(pg.stats + 3, 1ull);
+}
+
+__device__ __forceinline__ void wave_stats(const PathG& pg, unsigned ev, unsigned st, unsigned fw) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ev += __shfl_xor(ev, o);
+    st += __shfl_xor(st, o);
+    fw += __shfl_xor(fw, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (ev) atomicAdd(pg.stats + 0, (unsigned long long)ev);
+    if (st) atomicAdd(pg.stats + 1, (unsigned long long)st);
+    if (fw) atomicAdd(pg.stats + 2, (unsigned long long)fw);
+  }
+}
+
+// Camera paths: one per (pixel, sample), started at the volume box entry.
+__global__ __launch_bounds__(256) void path_init_kernel(PathG pg, CamG cam, int W, int H) {
+  const long long total = (long long)W * H * pg.spp;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  PRay r{};
+  bool live = false;
+  if (id < total) {
+    const uint32_t pid = (uint32_t)id;
+    const int pix = (int)(id / pg.spp);
+    double d[3];
+    camera_ray(cam, pix % W, pix / W, d);
+    const double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {pg.box[0], pg.box[1], pg.box[2]};
+    double t_in, t_out;
+    if (!pg.vacuum && clip_box(cam.eye, d, lo, hi, t_in, t_out)) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        r.x[a] = (float)(cam.eye[a] + t_in * d[a]);
+        r.w[a] = (float)d[a];
+        r.t[a] = 1.f;
+      }
+      r.pid = pid;
+      r.brick = -1;
+      live = true;
+    } else {
+      add_contrib(pg, pid, pg.B, pg.Le[0], pg.Le[1], pg.Le[2]);
+    }
+  }
+  const PRay none{};
+  emit2(pg, r, live, none, false);
+}
+
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, const float4* __restrict__ tf,
+                                                         const PRay* __restrict__ in, int n_in) {
+  extern __shared__ float4 tf_lds[];
+  float4* tfb = tf_lds;
+  float4* tfs = tf_lds + sc.ntf;
+  stage_tf(tf, sc.ntf, tfb, tfs, threadIdx.x, 256);
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  PRay ra{}, rb{};
+  bool ha = false, hb = false;
+  unsigned ev = 0, st = 0, fw = 0;
+  if (i < n_in) {
+    PRay r = in[i];
+    const float inv_sbar = 1.f / pg.sbar;
+    if (r.meta & kShadowRay) {
+      const int slot = (int)((r.meta >> 16) & 0xff);
+      for (int it = 0;; ++it) {
+        if (it == kStepsPerWave) {  // keep it for the next wave
+          ra = r;
+          ha = true;
+          break;
+        }
+        if (!(r.meta & kPendingEvent)) {
+          const uint4 q = philox(r.pid, r.e, 1u, r.meta & 0xffffu, pg.seed, kPathKey1);
+          const float s = -logf(u01(q.x)) / pg.sbar;
+          r.b += s;
+          ++st;
+          if (r.b >= r.c) {
+            add_contrib(pg, r.pid, slot, r.t[0] * r.a, r.t[1] * r.a, r.t[2] * r.a);
+            break;
+          }
+#pragma unroll
+          for (int a = 0; a < 3; ++a) r.x[a] = fmaf(s, r.w[a], r.x[a]);
+          r.meta |= kPendingEvent;
+        }
+        const int owner = locate(sc, pg, r.x, r.brick);
+        if (owner >= 0 && owner != r.brick) {
+          r.brick = owner;
+          ra = r;
+          ha = true;
+          ++fw;
+          break;
+        }
+        float sigma = 0.f, alb[3];
+        if (owner >= 0) medium<T, WIDE>(sc, pg.bricks[owner], tfb, tfs, r.x, sigma, alb);
+        r.a *= 1.f - sigma * inv_sbar;
+        r.meta = (r.meta & ~(kPendingEvent | 0xffffu)) | (((r.meta & 0xffffu) + 1u) & 0xffffu);
+        if (r.a == 0.f) break;  // nothing more can reach the light (the slot stays 0)
+      }
+    } else {
+      for (int it = 0;; ++it) {
+        if (it == kStepsPerWave) {
+          ra = r;
+          ha = true;
+          break;
+        }
+        if (!(r.meta & kPendingEvent)) {
+          const uint4 q = philox(r.pid, r.e, 0u, 0u, pg.seed, kPathKey1);
+          const float t = -logf(u01(q.x)) / pg.sbar;
+          if (t >= exit_dist(pg, r.x, r.w)) {  // leaves the volume
+            add_contrib(pg, r.pid, pg.B, r.t[0] * pg.Le[0], r.t[1] * pg.Le[1], r.t[2] * pg.Le[2]);
+            break;
+          }
+#pragma unroll
+          for (int a = 0; a < 3; ++a) r.x[a] = fmaf(t, r.w[a], r.x[a]);
+          r.a = u01(q.y);
+          r.b = u01(q.z);
+          r.c = u01(q.w);
+          r.meta |= kPendingEvent;
+        }
+        const int owner = locate(sc, pg, r.x, r.brick);
+        if (owner >= 0 && owner != r.brick) {
+          r.brick = owner;
+          ra = r;
+          ha = true;
+          ++fw;
+          break;
+        }
+        ++ev;
+        float sigma = 0.f, alb[3] = {0.f, 0.f, 0.f};
+        if (owner >= 0) medium<T, WIDE>(sc, pg.bricks[owner], tfb, tfs, r.x, sigma, alb);
+        r.meta &= ~kPendingEvent;
+        const uint32_t e = r.e++;
+        if (r.a < sigma / pg.sbar) {  // real collision
+          const int k = (int)((r.meta >> 16) & 0xff);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) r.t[a] *= alb[a];
+          PRay s{};
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            s.x[a] = r.x[a];
+            s.w[a] = pg.l[a];
+            s.t[a] = r.t[a] * pg.Ll[a];
+          }
+          s.a = 1.f;
+          s.b = 0.f;
+          s.c = exit_dist(pg, r.x, pg.l);
+          s.pid = r.pid;
+          s.e = e;
+          s.meta = kShadowRay | ((uint32_t)k << 16);
+          s.brick = owner;
+          rb = s;
+          hb = true;
+          if (k + 1 >= pg.B) break;  // the path ends at its last real collision
+          r.meta = (r.meta & ~(0xffu << 16)) | ((uint32_t)(k + 1) << 16);
+          const float z = 1.f - 2.f * r.b;
+          const float rr = sqrtf(fmaxf(0.f, 1.f - z * z));
+          float sp, cp;
+          sincosf(6.28318530717958647692f * r.c, &sp, &cp);
+          r.w[0] = rr * cp;
+          r.w[1] = rr * sp;
+          r.w[2] = z;
+          ra = r;
+          ha = true;
+          break;
+        }
+      }
+    }
+  }
+  emit2(pg, ra, ha, rb, hb);
+  wave_stats(pg, ev, st, fw);
+}
+
+// Pixel radiance: the contributions of its paths, summed in slot order, then
+// averaged over its samples.
+__global__ __launch_bounds__(256) void path_resolve_kernel(PathG pg, int n_pixels, float4* __restrict__ out_rgba,
+                                                           float* __restrict__ out_depth) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= n_pixels) return;
+  float sr = 0.f, sg = 0.f, sb = 0.f;
+  for (int s = 0; s < pg.spp; ++s) {
+    const float4* c = pg.contrib + ((size_t)p * pg.spp + s) * (pg.B + 1);
+    float lr = 0.f, lg = 0.f, lb = 0.f;
+    for (int k = 0; k <= pg.B; ++k) {
+      const float4 v = c[k];
+      lr += v.x;
+      lg += v.y;
+      lb += v.z;
+    }
+    sr += lr;
+    sg += lg;
+    sb += lb;
+  }
+  const float inv = 1.f / (float)pg.spp;
+  out_rgba[p] = make_float4(sr * inv, sg * inv, sb * inv, 1.f);
+  out_depth[p] = INFINITY;
+}
+
+struct PathState {
+  PRay* pool[2] = {nullptr, nullptr};
+  size_t cap = 0;  // records per pool
+  float4* contrib = nullptr;
+  size_t contrib_cap = 0;
+  BrickG* d_bricks = nullptr;
+  int brick_cap = 0;
+  int* d_count = nullptr;  // [0]: pool size
+  unsigned long long* d_stats = nullptr;
+  int* h_count = nullptr;  // pinned
+};
+
+void path_state_free(PathState* p) {
+  if (!p) return;
+  dev_free(p->pool[0]);
+  dev_free(p->pool[1]);
+  dev_free(p->contrib);
+  dev_free(p->d_bricks);
+  dev_free(p->d_count);
+  dev_free(p->d_stats);
+  if (p->h_count) (void)hipHostFree(p->h_count);
+  delete p;
+}
+
+template <typename T, bool WIDE>
+static void launch_trace(const SceneG& sc, const PathG& pg, const float4* tf, const PRay* in, int n, size_t lds,
+                         hipStream_t st) {
+  hipLaunchKernelGGL((path_trace_kernel<T, WIDE>), dim3((unsigned)((n + 255) / 256)), dim3(256), lds, st, sc, pg,
+                     tf, in, n);
+}
+
+}  // namespace dpr
+
+using namespace dpr;
+
+extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, dpr_frame out,
+                                      dpr_path_stats* stats) {
+  if (!w || !prm || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: NULL argument");
+  if (!w->committed) return fail(DPR_ERR_INVALID_STATE, "dpr_render_path: world not committed");
+  if (!w->tf_set) return fail(DPR_ERR_INVALID_STATE, "dpr_render_path: no transfer function set");
+  if (!w->cam_set) return fail(DPR_ERR_INVALID_STATE, "dpr_render_path: no camera set");
+  if (out->dev != w->dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: frame of another device");
+  if (out->w != w->cam.width || out->h != w->cam.height)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: frame %dx%d != camera %dx%d", out->w, out->h,
+                w->cam.width, w->cam.height);
+  if (prm->max_bounces < 1 || prm->max_bounces > 255)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: max_bounces %d outside [1, 255]", prm->max_bounces);
+  if (prm->spp < 1) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: spp %d", prm->spp);
+  double ln = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(prm->light_dir[a]) || !(prm->light_rgb[a] >= 0.f) || !std::isfinite(prm->light_rgb[a]) ||
+        !(prm->env_rgb[a] >= 0.f) || !std::isfinite(prm->env_rgb[a]))
+      return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: light or environment not finite and >= 0");
+    ln += (double)prm->light_dir[a] * prm->light_dir[a];
+  }
+  if (!(ln > 0.0)) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_path: light_dir is zero");
+  const int K = (int)w->bricks.size();
+  for (const auto& b : w->bricks)
+    if (b.dtype != w->bricks[0].dtype)
+      return fail(DPR_ERR_UNSUPPORTED, "dpr_render_path: bricks of different element types");
+  const long long n_paths = (long long)out->w * out->h * prm->spp;
+  const int B = prm->max_bounces;
+  const long long slots = n_paths * (B + 1);
+  if (n_paths > 0x7fffffffll || slots > 0x7fffffffll)
+    return fail(DPR_ERR_UNSUPPORTED, "dpr_render_path: %lld paths x %d slots exceed 2^31", n_paths, B + 1);
+  hipStream_t st = w->dev->stream;
+  if (!w->path) w->path = new PathState;
+  PathState* ps = w->path;
+  dpr_status s;
+  if ((size_t)slots > ps->cap) {
+    DPR_HIP(hipStreamSynchronize(st));
+    dev_free(ps->pool[0]);
+    dev_free(ps->pool[1]);
+    ps->pool[0] = ps->pool[1] = nullptr;
+    ps->cap = 0;
+    if ((s = dev_alloc((void**)&ps->pool[0], (size_t)slots * sizeof(PRay), "path ray pool")) != DPR_OK) return s;
+    if ((s = dev_alloc((void**)&ps->pool[1], (size_t)slots * sizeof(PRay), "path ray pool")) != DPR_OK) return s;
+    ps->cap = (size_t)slots;
+  }
+  if ((size_t)slots > ps->contrib_cap) {
+    DPR_HIP(hipStreamSynchronize(st));
+    dev_free(ps->contrib);
+    ps->contrib = nullptr;
+    ps->contrib_cap = 0;
+    if ((s = dev_alloc((void**)&ps->contrib, (size_t)slots * sizeof(float4), "path contributions")) != DPR_OK)
+      return s;
+    ps->contrib_cap = (size_t)slots;
+  }
+  if (K > ps->brick_cap) {
+    DPR_HIP(hipStreamSynchronize(st));
+    dev_free(ps->d_bricks);
+    ps->d_bricks = nullptr;
+    if ((s = dev_alloc((void**)&ps->d_bricks, (size_t)K * sizeof(BrickG), "path bricks")) != DPR_OK) return s;
+    ps->brick_cap = K;
+  }
+  if (!ps->d_count) {
+    if ((s = dev_alloc((void**)&ps->d_count, 2 * sizeof(int), "path pool size")) != DPR_OK) return s;
+    if ((s = dev_alloc((void**)&ps->d_stats, 4 * sizeof(unsigned long long), "path stats")) != DPR_OK) return s;
+    DPR_HIP(hipHostMalloc((void**)&ps->h_count, 2 * sizeof(int), hipHostMallocDefault));
+  }
+  std::vector<BrickG> views(K);
+  bool wide = false;
+  for (int i = 0; i < K; ++i) {
+    views[i] = w->bricks[i].device_view(false);
+    wide |= views[i].wide;
+  }
+  // the views are staged through pageable memory: wait for the copy before they change
+  DPR_HIP(hipMemcpyAsync(ps->d_bricks, views.data(), (size_t)K * sizeof(BrickG), hipMemcpyHostToDevice, st));
+
+  const SceneG sc = make_scene(w);
+  float amax = 0.f;
+  // the majorant: D times the largest TF opacity (the TF is staged on the host)
+  {
+    std::vector<float4> tfh(w->ntf);
+    DPR_HIP(hipMemcpyAsync(tfh.data(), w->tf_dev, (size_t)w->ntf * sizeof(float4), hipMemcpyDeviceToHost, st));
+    DPR_HIP(hipStreamSynchronize(st));
+    for (const auto& v : tfh) amax = std::max(amax, v.w);
+  }
+  PathG pg{};
+  pg.bricks = ps->d_bricks;
+  pg.nbricks = K;
+  pg.sbar = sc.density * amax;
+  for (int a = 0; a < 3; ++a) pg.box[a] = (float)((double)w->dims[a] * sc.h);
+  const double inv_l = 1.0 / std::sqrt(ln);
+  const float inv4pi = (float)(1.0 / (4.0 * M_PI));
+  for (int a = 0; a < 3; ++a) {
+    pg.l[a] = (float)(-(double)prm->light_dir[a] * inv_l);
+    pg.Ll[a] = prm->light_rgb[a] * inv4pi;
+    pg.Le[a] = prm->env_rgb[a];
+  }
+  pg.B = B;
+  pg.spp = prm->spp;
+  pg.seed = prm->seed;
+  pg.contrib = ps->contrib;
+  pg.out_count = ps->d_count;
+  pg.out_cap = (int)ps->cap;
+  pg.stats = ps->d_stats;
+  DPR_HIP(hipMemsetAsync(ps->contrib, 0, (size_t)slots * sizeof(float4), st));
+  DPR_HIP(hipMemsetAsync(ps->d_count, 0, 2 * sizeof(int), st));
+  DPR_HIP(hipMemsetAsync(ps->d_stats, 0, 4 * sizeof(unsigned long long), st));
+
+  int cur = 0;
+  pg.out = ps->pool[cur];
+  pg.vacuum = !(pg.sbar > 0.f);
+  const CamG cam = make_cam(w->cam);
+  hipLaunchKernelGGL(path_init_kernel, dim3((unsigned)((n_paths + 255) / 256)), dim3(256), 0, st, pg, cam, out->w,
+                     out->h);
+  DPR_HIP(hipGetLastError());
+  DPR_HIP(hipMemcpyAsync(ps->h_count, ps->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
+  DPR_HIP(hipStreamSynchronize(st));
+  int n = ps->h_count[0];
+  const size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
+  const bool f16 = K > 0 && w->bricks[0].dtype == DPR_F16;
+  int waves = 0;
+  while (n > 0) {
+    if (++waves > kMaxWaves) return fail(DPR_ERR_DEVICE, "dpr_render_path: more than %d waves", kMaxWaves);
+    const PRay* in = ps->pool[cur];
+    cur ^= 1;
+    pg.out = ps->pool[cur];
+    DPR_HIP(hipMemsetAsync(ps->d_count, 0, sizeof(int), st));
+    if (f16)
+      wide ? launch_trace<__half, true>(sc, pg, w->tf_dev, in, n, lds, st)
+           : launch_trace<__half, false>(sc, pg, w->tf_dev, in, n, lds, st);
+    else
+      wide ? launch_trace<float, true>(sc, pg, w->tf_dev, in, n, lds, st)
+           : launch_trace<float, false>(sc, pg, w->tf_dev, in, n, lds, st);
+    DPR_HIP(hipGetLastError());
+    DPR_HIP(hipMemcpyAsync(ps->h_count, ps->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
+    DPR_HIP(hipStreamSynchronize(st));
+    n = ps->h_count[0];
+    if ((size_t)n > ps->cap) return fail(DPR_ERR_DEVICE, "dpr_render_path: ray pool overflow (%d > %zu)", n, ps->cap);
+  }
+  const int P = out->w * out->h;
+  hipLaunchKernelGGL(path_resolve_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, pg, P,
+                     (float4*)out->rgba, out->depth);
+  DPR_HIP(hipGetLastError());
+  unsigned long long hs[4] = {0, 0, 0, 0};
+  DPR_HIP(hipMemcpyAsync(hs, ps->d_stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+  DPR_HIP(hipStreamSynchronize(st));
+  if (hs[3]) return fail(DPR_ERR_DEVICE, "dpr_render_path: %llu rays did not fit the pool", hs[3]);
+  if (stats) {
+    stats->paths = n_paths;
+    stats->events = (int64_t)hs[0];
+    stats->shadow_steps = (int64_t)hs[1];
+    stats->forwards = (int64_t)hs[2];
+    stats->waves = waves;
+  }
+  return DPR_OK;
+}

@@ -388,6 +388,7 @@ void dpr_world_release(dpr_world w) {
   }
   for (auto f : w->partials) dpr_frame_release(f);
   if (w->batch) batch_state_free(w->batch);
+  if (w->path) path_state_free(w->path);
   dev_free(w->tf_dev);
   if (w->tf_host) (void)hipHostFree(w->tf_host);
   if (w->tf_ev) (void)hipEventDestroy(w->tf_ev);

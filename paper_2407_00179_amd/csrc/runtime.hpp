@@ -100,6 +100,8 @@ struct Brick {
 
 struct BatchState;  // persistent batched renderer (k_batch.hip)
 void batch_state_free(BatchState*);
+struct PathState;  // ray pools of the path tracer (k_path.hip)
+void path_state_free(PathState*);
 
 }  // namespace dpr
 
@@ -124,6 +126,7 @@ struct dpr_world_t {
   // partial frames of dpr_render_frame (one per brick)
   std::vector<dpr_frame> partials;
   dpr::BatchState* batch = nullptr;
+  dpr::PathState* path = nullptr;
   uint64_t geo_version = 1;  // bumped when a brick is added (invalidates batch item lists)
   // pinned staging for transfer-function uploads; tf_ev marks the last upload
   float4* tf_host = nullptr;

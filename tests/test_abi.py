@@ -63,6 +63,7 @@ def test_null_handles_are_invalid_arguments(N):
     assert N.lib.dpr_frame_map(None, None, None) == -1
     assert N.lib.dpr_set_camera(None, None) == -1
     assert N.lib.dpr_render_deep(None, 0, None) == -1
+    assert N.lib.dpr_render_path(None, None, None, None) == -1
     assert N.lib.dpr_set_isosurface(None, 1, 0.5, 0.2, 0.8) == -1
     assert N.lib.dpr_composite_deep(None, None, 1, None) == -1
     assert N.lib.dpr_deep_frame_create(None, 4, 4, 2, C.byref(C.c_void_p())) == -1
