@@ -14,8 +14,9 @@ processed before termination, skipped ones included), in Msamples/s.
 Extra sections (same JSON line): the K=128 compositor at 3840x2160, the batched
 persistent renderer against plain per-brick launches on the 27-brick 16-camera
 workload, the backward/forward time ratio of the differentiable renderer, deep
-(multi-fragment) frames of an interleaved 8-rank partition, and the opaque
-iso-surface mixed with the volume.
+(multi-fragment) frames of an interleaved 8-rank partition, the opaque
+iso-surface mixed with the volume, and data-parallel path tracing with rays
+forwarded between bricks.
 
 The CPU baseline (the FP64 oracle, not tuned) runs first, before any GPU use,
 on a bounded pixel sample of the default workload, over a fork pool of host cores.
@@ -414,6 +415,54 @@ def bench_iso(args, dpr, torch, dev, bricks, dims, tf, cfg, cam):
     return out
 
 
+def bench_path(args, dpr, torch, dev):
+    """Data-parallel path tracing of the default 512^3 volume at 1024x1024, 1 path per
+    pixel, up to 4 real collisions, one directional light: the whole volume as 1
+    brick, 2x2x2 bricks and 4x4x4 bricks (rays handed between bricks in waves).
+    The images must agree bit for bit."""
+    cfg = get_config("cfg2")
+    dims = cfg.dims
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+    tf = make_tf(cfg.seeds["tf"])
+    cam = orbit_camera(dims, *cfg.image)
+    reps = max(3, args.steps)
+    out = {}
+    ref = None
+    for parts in ((1, 1, 1), (2, 2, 2), (4, 4, 4)):
+        w = dpr.World(dev, dims)
+        w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
+        for lo, hi in even_split(dims, parts):
+            b = extract_brick(vol, dims, lo, hi, 1)
+            w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)
+        w.commit()
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+        w.set_camera(cam)
+        f = dpr.Frame(dev, cam.width, cam.height)
+        st = w.render_path(f, max_bounces=4, spp=1, seed=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            w.render_path(f, max_bounces=4, spp=1, seed=1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        img = f.rgba.clone()
+        same = True if ref is None else bool(torch.equal(img, ref))
+        if ref is None:
+            ref = img
+        n = int(np.prod(parts))
+        out[f"{n}_bricks"] = dict(ms_frame=ms, mpaths_per_s=st["paths"] / ms / 1e3,
+                                  mevents_per_s=(st["events"] + st["shadow_steps"]) / ms / 1e3, waves=st["waves"],
+                                  forwards=st["forwards"], events=st["events"], shadow_steps=st["shadow_steps"],
+                                  identical_to_1_brick=same)
+        f.release()
+        w.release()
+        torch.cuda.empty_cache()
+    out["workload"] = ("512^3 FP32 volume, 1024x1024, 1 path per pixel, <= 4 real collisions, delta tracking + "
+                       "ratio-tracked shadow rays; the volume as 1, 8 and 64 bricks")
+    return out
+
+
 def bench_train(args, dpr, torch, dev):
     """256^3 FP32 density grid + 256-entry TF as parameters, 16 cameras at 512x512:
     the differentiable forward (with checkpoint stores) and the adjoint march."""
@@ -478,7 +527,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batch,cfg3,train,composite128,deep,iso")
+    ap.add_argument("--sections", default="batch,cfg3,train,composite128,deep,iso,path")
     ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device-to-device copy first (scales HBM byte counters)")
@@ -577,6 +626,9 @@ def main():
     if "iso" in secs:
         log("GPU: iso-surface on the default workload")
         line["iso_cfg2"] = bench_iso(args, dpr, torch, dev, bricks, dims, tf, cfg, cam)
+    if "path" in secs:
+        log("GPU: data-parallel path tracing")
+        line["path_cfg2"] = bench_path(args, dpr, torch, dev)
     if "deep" in secs:
         log("GPU: deep frames of an interleaved 8-rank partition")
         line["deep_8ranks"] = bench_deep(args, dpr, torch, dev)
