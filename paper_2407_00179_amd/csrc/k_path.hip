@@ -42,10 +42,16 @@ constexpr uint32_t kShadowRay = 1u << 31, kPendingEvent = 1u << 30;
 constexpr uint32_t kPathKey1 = 0x243F6A88u;
 constexpr int kStepsPerWave = 1 << 16;  // bound on one ray's steps in one wave
 constexpr int kMaxWaves = 1 << 14;
+constexpr int kOwnerShift = 4;            // owner blocks of 16^3 cells
+constexpr int kWavesPerCheck = 4;         // waves enqueued between reads of the pool size
 
 struct PathG {
   const BrickG* bricks;
   int nbricks;
+  // owner of each block of kOwnerCells^3 cells: a brick that holds all of it, -1
+  // for a gap, -2 where bricks meet inside the block (then the bricks are searched)
+  const int16_t* owner;
+  int odim[3];
   float sbar;
   float box[3];
   float l[3];   // unit direction towards the light
@@ -58,7 +64,7 @@ struct PathG {
   PRay* out;
   int* out_count;
   int out_cap;
-  unsigned long long* stats;  // events, shadow steps, forwards, pool overflows
+  unsigned long long* stats;  // events, shadow steps, forwards, pool overflows, waves with rays
 };
 
 // Philox4x32-10 (Salmon et al., SC 2011): ten rounds of two 32x32->64 products,
@@ -108,6 +114,9 @@ __device__ __forceinline__ int locate(const SceneG& sc, const PathG& pg, const f
            c[2] < b.ohi[2];
   };
   if (hint >= 0 && inside(hint)) return hint;
+  const int o = pg.owner[((c[2] >> kOwnerShift) * pg.odim[1] + (c[1] >> kOwnerShift)) * pg.odim[0] +
+                         (c[0] >> kOwnerShift)];
+  if (o != -2) return o;
   for (int i = 0; i < pg.nbricks; ++i)
     if (inside(i)) return i;
   return -1;
@@ -208,18 +217,28 @@ __global__ __launch_bounds__(256) void path_init_kernel(PathG pg, CamG cam, int 
   emit2(pg, r, live, none, false);
 }
 
+// n_in: device count of the input pool (written by the previous wave).  A resident
+// grid walks it in chunks of one wave's 64 records, so the loop bound is the same
+// for all lanes of a wave and the appends stay convergent.
 template <typename T, bool WIDE>
 __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, const float4* __restrict__ tf,
-                                                         const PRay* __restrict__ in, int n_in) {
+                                                         const PRay* __restrict__ in,
+                                                         const int* __restrict__ n_in_dev) {
   extern __shared__ float4 tf_lds[];
   float4* tfb = tf_lds;
   float4* tfs = tf_lds + sc.ntf;
   stage_tf(tf, sc.ntf, tfb, tfs, threadIdx.x, 256);
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int n_in = min(*n_in_dev, pg.out_cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n_in > 0) atomicAdd(pg.stats + 4, 1ull);
+  const int lane = threadIdx.x & 63;
+  const int wave0 = (blockIdx.x * 256 + threadIdx.x) & ~63;
+  const int stride = gridDim.x * 256;
+  unsigned ev = 0, st = 0, fw = 0;
+  for (int base = wave0; base < n_in; base += stride) {
+  const int i = base + lane;
   PRay ra{}, rb{};
   bool ha = false, hb = false;
-  unsigned ev = 0, st = 0, fw = 0;
   if (i < n_in) {
     PRay r = in[i];
     const float inv_sbar = 1.f / pg.sbar;
@@ -329,6 +348,7 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
     }
   }
   emit2(pg, ra, ha, rb, hb);
+  }
   wave_stats(pg, ev, st, fw);
 }
 
@@ -364,7 +384,11 @@ struct PathState {
   size_t contrib_cap = 0;
   BrickG* d_bricks = nullptr;
   int brick_cap = 0;
-  int* d_count = nullptr;  // [0]: pool size
+  int16_t* d_owner = nullptr;
+  size_t owner_cap = 0;
+  uint64_t owner_version = 0;
+  int odim[3] = {0, 0, 0};
+  int* d_count = nullptr;  // [0], [1]: sizes of the two pools
   unsigned long long* d_stats = nullptr;
   int* h_count = nullptr;  // pinned
 };
@@ -375,6 +399,7 @@ void path_state_free(PathState* p) {
   dev_free(p->pool[1]);
   dev_free(p->contrib);
   dev_free(p->d_bricks);
+  dev_free(p->d_owner);
   dev_free(p->d_count);
   dev_free(p->d_stats);
   if (p->h_count) (void)hipHostFree(p->h_count);
@@ -382,10 +407,9 @@ void path_state_free(PathState* p) {
 }
 
 template <typename T, bool WIDE>
-static void launch_trace(const SceneG& sc, const PathG& pg, const float4* tf, const PRay* in, int n, size_t lds,
-                         hipStream_t st) {
-  hipLaunchKernelGGL((path_trace_kernel<T, WIDE>), dim3((unsigned)((n + 255) / 256)), dim3(256), lds, st, sc, pg,
-                     tf, in, n);
+static void launch_trace(const SceneG& sc, const PathG& pg, const float4* tf, const PRay* in, const int* n,
+                         int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((path_trace_kernel<T, WIDE>), dim3((unsigned)grid), dim3(256), lds, st, sc, pg, tf, in, n);
 }
 
 }  // namespace dpr
@@ -454,8 +478,51 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   }
   if (!ps->d_count) {
     if ((s = dev_alloc((void**)&ps->d_count, 2 * sizeof(int), "path pool size")) != DPR_OK) return s;
-    if ((s = dev_alloc((void**)&ps->d_stats, 4 * sizeof(unsigned long long), "path stats")) != DPR_OK) return s;
+    if ((s = dev_alloc((void**)&ps->d_stats, 5 * sizeof(unsigned long long), "path stats")) != DPR_OK) return s;
     DPR_HIP(hipHostMalloc((void**)&ps->h_count, 2 * sizeof(int), hipHostMallocDefault));
+  }
+  // owner table of 16^3-cell blocks, rebuilt when bricks were added
+  int od[3];
+  for (int a = 0; a < 3; ++a) od[a] = (int)((w->dims[a] + (1 << kOwnerShift) - 1) >> kOwnerShift);
+  const size_t n_own = (size_t)od[0] * od[1] * od[2];
+  if (ps->owner_version != w->geo_version || ps->odim[0] != od[0] || ps->odim[1] != od[1] || ps->odim[2] != od[2]) {
+    std::vector<int16_t> own(n_own);
+    for (int bz = 0; bz < od[2]; ++bz)
+      for (int by = 0; by < od[1]; ++by)
+        for (int bx = 0; bx < od[0]; ++bx) {
+          const int64_t lo[3] = {(int64_t)bx << kOwnerShift, (int64_t)by << kOwnerShift, (int64_t)bz << kOwnerShift};
+          int64_t hi[3];
+          for (int a = 0; a < 3; ++a) hi[a] = std::min(lo[a] + (1 << kOwnerShift), w->dims[a]);
+          int found = -1, overlaps = 0;
+          bool whole = false;
+          for (int i = 0; i < K; ++i) {
+            const auto& b = w->bricks[i];
+            bool ov = true, con = true;
+            for (int a = 0; a < 3; ++a) {
+              ov &= b.olo[a] < hi[a] && lo[a] < b.ohi[a];
+              con &= b.olo[a] <= lo[a] && hi[a] <= b.ohi[a];
+            }
+            if (ov) {
+              ++overlaps;
+              found = i;
+              whole = con;
+            }
+          }
+          own[((size_t)bz * od[1] + by) * od[0] + bx] =
+              (int16_t)(overlaps == 0 ? -1 : (overlaps == 1 && whole ? found : -2));
+        }
+    if (n_own > ps->owner_cap) {
+      DPR_HIP(hipStreamSynchronize(st));
+      dev_free(ps->d_owner);
+      ps->d_owner = nullptr;
+      ps->owner_cap = 0;
+      if ((s = dev_alloc((void**)&ps->d_owner, n_own * sizeof(int16_t), "path owner table")) != DPR_OK) return s;
+      ps->owner_cap = n_own;
+    }
+    DPR_HIP(hipMemcpyAsync(ps->d_owner, own.data(), n_own * sizeof(int16_t), hipMemcpyHostToDevice, st));
+    DPR_HIP(hipStreamSynchronize(st));
+    for (int a = 0; a < 3; ++a) ps->odim[a] = od[a];
+    ps->owner_version = w->geo_version;
   }
   std::vector<BrickG> views(K);
   bool wide = false;
@@ -478,6 +545,8 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   PathG pg{};
   pg.bricks = ps->d_bricks;
   pg.nbricks = K;
+  pg.owner = ps->d_owner;
+  for (int a = 0; a < 3; ++a) pg.odim[a] = od[a];
   pg.sbar = sc.density * amax;
   for (int a = 0; a < 3; ++a) pg.box[a] = (float)((double)w->dims[a] * sc.h);
   const double inv_l = 1.0 / std::sqrt(ln);
@@ -496,7 +565,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   pg.stats = ps->d_stats;
   DPR_HIP(hipMemsetAsync(ps->contrib, 0, (size_t)slots * sizeof(float4), st));
   DPR_HIP(hipMemsetAsync(ps->d_count, 0, 2 * sizeof(int), st));
-  DPR_HIP(hipMemsetAsync(ps->d_stats, 0, 4 * sizeof(unsigned long long), st));
+  DPR_HIP(hipMemsetAsync(ps->d_stats, 0, 5 * sizeof(unsigned long long), st));
 
   int cur = 0;
   pg.out = ps->pool[cur];
@@ -510,21 +579,32 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   int n = ps->h_count[0];
   const size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   const bool f16 = K > 0 && w->bricks[0].dtype == DPR_F16;
-  int waves = 0;
+  // a resident grid walks whatever the previous wave left; the host reads the pool
+  // size only every kWavesPerCheck waves (later waves of a batch may find it empty)
+  const void* fn = f16 ? (wide ? (const void*)path_trace_kernel<__half, true> : (const void*)path_trace_kernel<__half, false>)
+                       : (wide ? (const void*)path_trace_kernel<float, true> : (const void*)path_trace_kernel<float, false>);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int grid = w->dev->cu_count * per_cu;
+  int enqueued = 0;
   while (n > 0) {
-    if (++waves > kMaxWaves) return fail(DPR_ERR_DEVICE, "dpr_render_path: more than %d waves", kMaxWaves);
-    const PRay* in = ps->pool[cur];
-    cur ^= 1;
-    pg.out = ps->pool[cur];
-    DPR_HIP(hipMemsetAsync(ps->d_count, 0, sizeof(int), st));
-    if (f16)
-      wide ? launch_trace<__half, true>(sc, pg, w->tf_dev, in, n, lds, st)
-           : launch_trace<__half, false>(sc, pg, w->tf_dev, in, n, lds, st);
-    else
-      wide ? launch_trace<float, true>(sc, pg, w->tf_dev, in, n, lds, st)
-           : launch_trace<float, false>(sc, pg, w->tf_dev, in, n, lds, st);
-    DPR_HIP(hipGetLastError());
-    DPR_HIP(hipMemcpyAsync(ps->h_count, ps->d_count, sizeof(int), hipMemcpyDeviceToHost, st));
+    for (int j = 0; j < kWavesPerCheck; ++j) {
+      if (++enqueued > kMaxWaves) return fail(DPR_ERR_DEVICE, "dpr_render_path: more than %d waves", kMaxWaves);
+      const PRay* in = ps->pool[cur];
+      const int* n_in = ps->d_count + cur;
+      cur ^= 1;
+      pg.out = ps->pool[cur];
+      pg.out_count = ps->d_count + cur;
+      DPR_HIP(hipMemsetAsync(pg.out_count, 0, sizeof(int), st));
+      if (f16)
+        wide ? launch_trace<__half, true>(sc, pg, w->tf_dev, in, n_in, grid, lds, st)
+             : launch_trace<__half, false>(sc, pg, w->tf_dev, in, n_in, grid, lds, st);
+      else
+        wide ? launch_trace<float, true>(sc, pg, w->tf_dev, in, n_in, grid, lds, st)
+             : launch_trace<float, false>(sc, pg, w->tf_dev, in, n_in, grid, lds, st);
+      DPR_HIP(hipGetLastError());
+    }
+    DPR_HIP(hipMemcpyAsync(ps->h_count, ps->d_count + cur, sizeof(int), hipMemcpyDeviceToHost, st));
     DPR_HIP(hipStreamSynchronize(st));
     n = ps->h_count[0];
     if ((size_t)n > ps->cap) return fail(DPR_ERR_DEVICE, "dpr_render_path: ray pool overflow (%d > %zu)", n, ps->cap);
@@ -533,7 +613,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   hipLaunchKernelGGL(path_resolve_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, pg, P,
                      (float4*)out->rgba, out->depth);
   DPR_HIP(hipGetLastError());
-  unsigned long long hs[4] = {0, 0, 0, 0};
+  unsigned long long hs[5] = {0, 0, 0, 0, 0};
   DPR_HIP(hipMemcpyAsync(hs, ps->d_stats, sizeof(hs), hipMemcpyDeviceToHost, st));
   DPR_HIP(hipStreamSynchronize(st));
   if (hs[3]) return fail(DPR_ERR_DEVICE, "dpr_render_path: %llu rays did not fit the pool", hs[3]);
@@ -542,7 +622,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
     stats->events = (int64_t)hs[0];
     stats->shadow_steps = (int64_t)hs[1];
     stats->forwards = (int64_t)hs[2];
-    stats->waves = waves;
+    stats->waves = (int32_t)hs[4];
   }
   return DPR_OK;
 }
