@@ -322,7 +322,9 @@ typedef struct {
  * world with TF and camera and one element type for all bricks.  Device memory:
  * two ray pools of 64 B x paths x (max_bounces + 1) and 16 B x paths x
  * (max_bounces + 1) of contributions, kept by the world for later calls.
- * Synchronises (the host reads the size of every wave).  stats may be NULL.    */
+ * Synchronises (the host reads the pool size every few waves).  Of the render
+ * flags only DPR_FLAG_WIDE_OFFSETS applies (64-bit voxel offsets on every brick;
+ * the same image).  stats may be NULL.                                          */
 dpr_status dpr_render_path(dpr_world, const dpr_path_params* params, dpr_frame out, dpr_path_stats* stats);
 
 /* ---------------------------------------------------------------- training */

@@ -527,7 +527,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   std::vector<BrickG> views(K);
   bool wide = false;
   for (int i = 0; i < K; ++i) {
-    views[i] = w->bricks[i].device_view(false);
+    views[i] = w->bricks[i].device_view(false, w->params.flags & DPR_FLAG_WIDE_OFFSETS);
     wide |= views[i].wide;
   }
   // the views are staged through pageable memory: wait for the copy before they change
