@@ -156,6 +156,43 @@ def test_macrocells_and_majorants_bitwise(gpu_lib, dpr):
         w.release()
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_ghost_width_does_not_change_a_bit(gpu_lib, dpr, dtype):
+    """Ghost layers of 1, 2 or 3 voxels give the same frames, and each its oracle
+    ranges (a window clipped to the stored range sees more voxels of a wider ghost
+    past a partial last macrocell)."""
+    dims = (70, 45, 38)
+    vol, tf = _small_case(dims, seed=33, nb=5, dtype=dtype)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 48, 40)
+    boxes = kd_split(dims, 6, seed=4, max_ratio=4.0)
+    outs = []
+    for ghost in (1, 2, 3):
+        w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=8, ghost=ghost)
+        f = dpr.Frame(gpu_lib, cam.width, cam.height)
+        w.render_frame(f)
+        parts = []
+        for i in range(len(boxes)):
+            pf = dpr.Frame(gpu_lib, cam.width, cam.height)
+            w.render_partial(i, pf)
+            parts.append(frame_np(pf)[0])
+            pf.release()
+        ranges = [w.macrocells(i) for i in range(len(boxes))]
+        outs.append((frame_np(f)[:2], parts, ranges))
+        f.release()
+        w.release()
+    for frame, parts, _ in outs[1:]:
+        assert np.array_equal(frame[0], outs[0][0][0]) and np.array_equal(frame[1], outs[0][0][1])
+        for a, b in zip(parts, outs[0][1]):
+            assert np.array_equal(a, b)
+    for ghost, (_, _, ranges) in zip((1, 2, 3), outs):
+        for i, (lo, hi) in enumerate(boxes):
+            b = extract_brick(vol, dims, lo, hi, ghost)
+            want = oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, 8)
+            assert np.array_equal(ranges[i][0], want), (ghost, i)
+            assert np.array_equal(ranges[i][1], oracle.majorants(want, tf)), (ghost, i)
+
+
 @pytest.mark.parametrize("dims,dtype", [((150, 9, 7), np.float32), ((300, 8, 6), np.float16),
                                         ((520, 6, 5), np.float32), ((1100, 5, 4), np.float32)])
 def test_macrocells_wide_bricks(gpu_lib, dpr, dims, dtype):
