@@ -15,23 +15,28 @@ and the transfer function of C7:
   RGB at v(x); isotropic phase function 1/(4 pi); no emission.  Light: one
   directional light (radiance L_l, travelling along l_dir) and a constant
   environment radiance L_e seen by rays leaving the volume box.
-* Majorant: one constant sigma_bar = D max_j A_j over the table, so the tentative
-  collisions of a path do not depend on how the volume is split into bricks.
+* Majorant: piecewise constant on the global grid of 16^3-cell blocks: block b
+  has sigma_bar_b = D m_b, with m_b the transfer-function majorant (C13, decided
+  in FP32) of the value range over voxels [16 b - 1, 16 b + 16] per axis.  The
+  grid is global, so the tentative collisions of a path do not depend on how the
+  volume is split into bricks; a block with m_b = 0 holds no tentative collision.
 * Random numbers: Philox4x32-10 (``rng.py``), key (seed, 0x243F6A88), counter
   (path, event, kind, step).  Path id = (row * width + column) * spp + sample;
   event e counts the tentative collisions of the path; one draw per event gives
   u0 (free flight), u1 (real or null), u2, u3 (new direction).
 * Camera ray through the pixel centre (C4), started at its entry t_in into the
   volume box; a ray that misses the box sees L_e.
-* Delta tracking: from x along w, the tentative point is q = x + t w with
-  t = -ln(u0) / sigma_bar.  If t >= the distance to the box exit, the path
-  leaves: it adds thr L_e.  Otherwise q is real when u1 < sigma(q) / sigma_bar;
-  else null, and the flight goes on from q.
+* Delta tracking: from x along w, walk the blocks (a 3D DDA), accumulating
+  sigma_bar_b times the length in each, until the sum reaches tau = -ln(u0); the
+  tentative point q is where it does.  If the walk leaves the box first, the path
+  leaves: it adds thr L_e.  Otherwise q is real when u1 < sigma(q) / sigma_bar(q)
+  (the majorant of the block holding q's cell; 0 / 0 counts as null); else null,
+  and the flight goes on from q.
 * At the k-th real collision (k = 0, 1, ...): thr *= albedo(q); a shadow ray from
-  q towards the light (-l_dir) estimates the transmittance by ratio tracking,
-  steps s = -ln(u) / sigma_bar with u from counter (path, e, 1, step), T *=
-  1 - sigma / sigma_bar until the accumulated length reaches the box exit; the
-  path adds thr L_l T / (4 pi).  After B real collisions the path ends; else it
+  q towards the light (-l_dir) estimates the transmittance by ratio tracking:
+  flights of optical length -ln(u) (u from counter (path, e, 1, step)) under the
+  same block majorants, T *= 1 - sigma / sigma_bar at each tentative point, until
+  a flight leaves the box; the path adds thr L_l T / (4 pi).  After B real collisions the path ends; else it
   leaves q in the isotropic direction z = 1 - 2 u2, phi = 2 pi u3.
 * Pixel radiance = mean over its spp paths of the sum of the path's
   contributions (NEE terms in collision order, then the environment term).
@@ -67,6 +72,62 @@ def _draw(pid, e, kind, step, seed):
     return uniforms(philox4x32(ctr, key))
 
 
+BLOCK = 16
+
+
+def block_majorants(volume, dims, tf, params: RenderParams):
+    """sigma_bar per 16^3-cell block of the global grid -> (Mz, My, Mx) FP64."""
+    from .macrocell import macrocell_ranges, majorants
+    rng = macrocell_ranges(volume, (0, 0, 0), tuple(int(v) for v in dims), (0, 0, 0), BLOCK)
+    return params.density * majorants(rng, tf, params.tf_lo, params.tf_hi).astype(np.float64)
+
+
+def _block_of(q, dims, h):
+    cell = np.clip(np.floor(q / h).astype(np.int64), 0, np.array(dims) - 1)
+    return cell // BLOCK
+
+
+def _flight(x, w, target, grid, dims, h):
+    """Delta-tracking flight under the block majorants: distance t along w from x
+    at which the accumulated sigma_bar * length reaches target (inf if the walk
+    leaves the box first), and the smallest |accumulated - target| at a block
+    boundary (how close a block or exit decision came to going the other way)."""
+    n = x.shape[0]
+    dims_a = np.array(dims, dtype=np.int64)
+    box_hi = dims_a * h
+    t_box = _exit_distance(x, w, box_hi)
+    blk = _block_of(x, dims, h)
+    t = np.zeros(n)
+    acc = np.zeros(n)
+    out = np.full(n, np.inf)
+    margin = np.full(n, np.inf)
+    act = np.arange(n)
+    while act.size:
+        b = blk[act]
+        lo = b * BLOCK * h
+        hi = np.minimum((b + 1) * BLOCK, dims_a) * h
+        xa, wa = x[act], w[act]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ta = np.where(wa > 0, (hi - xa) / wa, np.where(wa < 0, (lo - xa) / wa, np.inf))
+        t_next = ta.min(axis=1)
+        seg_end = np.minimum(t_next, t_box[act])
+        sb = grid[b[:, 2], b[:, 1], b[:, 0]]
+        gain = sb * (seg_end - t[act])
+        hit = acc[act] + gain >= target[act]
+        hi_idx = act[hit]
+        out[hi_idx] = t[hi_idx] + (target[hi_idx] - acc[hi_idx]) / sb[hit]
+        miss = ~hit
+        mi = act[miss]
+        acc[mi] += gain[miss]
+        t[mi] = seg_end[miss]
+        margin[mi] = np.minimum(margin[mi], np.abs(acc[mi] - target[mi]))
+        go_on = miss & (seg_end < t_box[act])
+        step = (ta == t_next[:, None]) & go_on[:, None]
+        blk[act] = b + np.where(step, np.sign(wa).astype(np.int64), 0)
+        act = act[go_on]
+    return out, margin
+
+
 def _exit_distance(x, w, box_hi):
     """Distance from points x inside the box [0, box_hi] to its exit along w."""
     t = np.full(x.shape[0], np.inf)
@@ -91,8 +152,8 @@ def trace_paths(volume, dims, tf, params: RenderParams, pp: PathParams, o, d, pi
     dims = tuple(int(v) for v in dims)
     h = 1.0 / max(dims)
     box_hi = np.array(dims, dtype=np.float64) * h
+    grid = block_majorants(volume, dims, tf, params)
     tf = np.asarray(tf, dtype=np.float64)
-    sbar = params.density * float(tf[:, 3].max())
     B = int(pp.max_bounces)
     ldir = -np.asarray(pp.light_dir, dtype=np.float64)
     ldir = ldir / np.linalg.norm(ldir)
@@ -111,11 +172,9 @@ def trace_paths(volume, dims, tf, params: RenderParams, pp: PathParams, o, d, pi
     bounce = np.zeros(act.size, dtype=np.int64)
     while act.size:
         u = _draw(pid[act], e, 0, np.zeros(act.size, dtype=np.int64), pp.seed)
-        t = -np.log(u[:, 0]) / sbar if sbar > 0 else np.full(act.size, np.inf)
-        t_exit = _exit_distance(x, w, box_hi)
-        if sbar > 0:
-            margin[act] = np.minimum(margin[act], sbar * np.abs(t - t_exit))
-        leave = t >= t_exit
+        t, fm = _flight(x, w, -np.log(u[:, 0]), grid, dims, h)
+        margin[act] = np.minimum(margin[act], fm)
+        leave = ~np.isfinite(t)
         L[act[leave]] += thr[leave] * L_e
         keep = ~leave
         act, x, w, thr, e, bounce, u, t = (a[keep] for a in (act, x, w, thr, e, bounce, u, t))
@@ -123,14 +182,17 @@ def trace_paths(volume, dims, tf, params: RenderParams, pp: PathParams, o, d, pi
             break
         q = x + t[:, None] * w
         sigma, alb = _medium(volume, dims, tf, params, q)
-        ratio = sigma / sbar
+        bq = _block_of(q, dims, h)
+        sq = grid[bq[:, 2], bq[:, 1], bq[:, 0]]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ratio = np.where(sq > 0, sigma / sq, 0.0)
         margin[act] = np.minimum(margin[act], np.abs(u[:, 1] - ratio))
         real = u[:, 1] < ratio
         ri = np.nonzero(real)[0]
         if ri.size:
             thr[ri] *= alb[ri]
-            T = _shadow(volume, dims, tf, params, q[ri], ldir, pid[act[ri]], e[ri], pp.seed, sbar, box_hi,
-                        margin, act[ri])
+            T = _shadow(volume, dims, tf, params, q[ri], ldir, pid[act[ri]], e[ri], pp.seed, grid, margin,
+                        act[ri])
             L[act[ri]] += thr[ri] * (L_l[None, :] * (T / (4.0 * math.pi))[:, None])
             bounce[ri] += 1
             z = 1.0 - 2.0 * u[ri, 2]
@@ -144,28 +206,32 @@ def trace_paths(volume, dims, tf, params: RenderParams, pp: PathParams, o, d, pi
     return L, margin
 
 
-def _shadow(volume, dims, tf, params, y0, l, pid, e, seed, sbar, box_hi, margin, rays):
-    """Ratio-tracking transmittance from y0 along l to the box exit."""
+def _shadow(volume, dims, tf, params, y0, l, pid, e, seed, grid, margin, rays):
+    """Ratio-tracking transmittance from y0 along l to the box exit, under the
+    block majorants."""
+    dims = tuple(int(v) for v in dims)
+    h = 1.0 / max(dims)
     n = y0.shape[0]
     T = np.ones(n)
-    s_exit = _exit_distance(y0, np.broadcast_to(l, y0.shape), box_hi)
-    s_acc = np.zeros(n)
     y = y0.copy()
+    lv = np.broadcast_to(l, y0.shape)
     idx = np.arange(n)
     k = 0
     while idx.size:
         u = _draw(pid[idx], e[idx], 1, np.full(idx.size, k), seed)[:, 0]
-        s = -np.log(u) / sbar
-        s_acc[idx] += s
-        margin[rays[idx]] = np.minimum(margin[rays[idx]], sbar * np.abs(s_acc[idx] - s_exit[idx]))
-        out = s_acc[idx] >= s_exit[idx]
+        t, fm = _flight(y[idx], lv[idx], -np.log(u), grid, dims, h)
+        margin[rays[idx]] = np.minimum(margin[rays[idx]], fm)
+        out = ~np.isfinite(t)
         idx = idx[~out]
-        s = s[~out]
+        t = t[~out]
         if not idx.size:
             break
-        y[idx] = y[idx] + s[:, None] * l[None, :]
+        y[idx] = y[idx] + t[:, None] * l[None, :]
         sigma, _ = _medium(volume, dims, tf, params, y[idx])
-        T[idx] *= 1.0 - sigma / sbar
+        b = _block_of(y[idx], dims, h)
+        sb = grid[b[:, 2], b[:, 1], b[:, 0]]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            T[idx] *= np.where(sb > 0, 1.0 - sigma / sb, 1.0)
         k += 1
     return T
 

@@ -11,15 +11,18 @@
 // order of rays in the pools, nor on the bricking: the tentative collisions come
 // from one constant majorant and a counter-based generator keyed by the path.
 //
-// Estimator (per path): delta tracking with majorant sbar = D max A; at a real
-// collision the throughput takes the albedo (TF colour), a shadow ray towards the
-// light tracks the transmittance by ratio tracking and adds thr * light * T / 4pi;
-// the path scatters isotropically until max_bounces real collisions; leaving the
-// volume box it adds thr * env.
+// Estimator (per path): delta tracking under a piecewise-constant majorant on the
+// global grid of 16^3-cell blocks (D times the TF majorant of the block's value
+// range; a flight walks the blocks with a 3D DDA, so empty blocks cost nothing);
+// at a real collision the throughput takes the albedo (TF colour), a shadow ray
+// towards the light tracks the transmittance by ratio tracking under the same
+// majorants and adds thr * light * T / 4pi; the path scatters isotropically until
+// max_bounces real collisions; leaving the volume box it adds thr * env.
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
+#include "majorant.h"
 #include "march.h"
 #include "runtime.hpp"
 
@@ -29,7 +32,7 @@ struct PRay {
   float x[3];
   float w[3];
   float t[3];     // path: throughput; shadow: weight (throughput * light / 4 pi)
-  float a, b, c;  // pending path event: u1, u2, u3; shadow: T, length so far, length to the box exit
+  float a, b, c;  // pending path event: u1, u2, u3; shadow: T in a
   uint32_t pid;   // path id
   uint32_t e;     // path: next event index; shadow: the event that spawned it
   uint32_t meta;  // bit 31 shadow, bit 30 pending, bits 16..23 bounce (path) or slot (shadow),
@@ -42,7 +45,7 @@ constexpr uint32_t kShadowRay = 1u << 31, kPendingEvent = 1u << 30;
 constexpr uint32_t kPathKey1 = 0x243F6A88u;
 constexpr int kStepsPerWave = 1 << 16;  // bound on one ray's steps in one wave
 constexpr int kMaxWaves = 1 << 14;
-constexpr int kOwnerShift = 4;            // owner blocks of 16^3 cells
+constexpr int kOwnerShift = 4;            // owner and majorant blocks of 16^3 cells
 constexpr int kWavesPerCheck = 4;         // waves enqueued between reads of the pool size
 
 struct PathG {
@@ -51,8 +54,9 @@ struct PathG {
   // owner of each block of kOwnerCells^3 cells: a brick that holds all of it, -1
   // for a gap, -2 where bricks meet inside the block (then the bricks are searched)
   const int16_t* owner;
-  int odim[3];
-  float sbar;
+  int odim[3];              // blocks per axis (owner table and majorant grid)
+  const float* sgrid;       // majorant per block: D * TF majorant of its value range
+  float sbar;               // D * max TF opacity (0: nothing can collide)
   float box[3];
   float l[3];   // unit direction towards the light
   float Ll[3];  // light radiance / (4 pi)
@@ -120,6 +124,58 @@ __device__ __forceinline__ int locate(const SceneG& sc, const PathG& pg, const f
   for (int i = 0; i < pg.nbricks; ++i)
     if (inside(i)) return i;
   return -1;
+}
+
+__device__ __forceinline__ float sbar_at(const SceneG& sc, const PathG& pg, const float q[3]) {
+  int b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    b[a] = min(max((int)floorf(q[a] * (float)sc.inv_h), 0), sc.dims[a] - 1) >> kOwnerShift;
+  return pg.sgrid[(b[2] * pg.odim[1] + b[1]) * pg.odim[0] + b[0]];
+}
+
+// Delta-tracking flight from x along w: walk the majorant blocks (3D DDA with
+// per-axis next-boundary distances, advanced by one block width per step),
+// accumulating majorant x length, until the sum reaches `target`; t_hit is the
+// distance there.  False when the walk leaves the volume box first.
+__device__ __forceinline__ bool flight(const SceneG& sc, const PathG& pg, const float x[3], const float w[3],
+                                       float target, float& t_hit) {
+  int b[3], step[3];
+  float tmax[3], tdel[3];
+  const float bw = (float)((double)(1 << kOwnerShift) * sc.h);  // block width
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    b[a] = min(max((int)floorf(x[a] * (float)sc.inv_h), 0), sc.dims[a] - 1) >> kOwnerShift;
+    const float lo = (float)((double)(b[a] << kOwnerShift) * sc.h);
+    const float hi = (float)((double)min((b[a] + 1) << kOwnerShift, sc.dims[a]) * sc.h);
+    step[a] = w[a] > 0.f ? 1 : (w[a] < 0.f ? -1 : 0);
+    tmax[a] = w[a] > 0.f ? (hi - x[a]) / w[a] : (w[a] < 0.f ? (lo - x[a]) / w[a] : INFINITY);
+    tdel[a] = w[a] != 0.f ? bw / fabsf(w[a]) : INFINITY;
+  }
+  const float t_box = exit_dist(pg, x, w);
+  float t = 0.f, acc = 0.f;
+  const int max_steps = 2 * (pg.odim[0] + pg.odim[1] + pg.odim[2]) + 8;
+  for (int it = 0; it < max_steps; ++it) {
+    const float tn = fminf(tmax[0], fminf(tmax[1], tmax[2]));
+    const float se = fminf(tn, t_box);
+    const float sb = pg.sgrid[(b[2] * pg.odim[1] + b[1]) * pg.odim[0] + b[0]];
+    const float gain = sb * (se - t);
+    if (acc + gain >= target) {
+      t_hit = t + (target - acc) / sb;
+      return true;
+    }
+    acc += gain;
+    t = se;
+    if (!(se < t_box)) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (tmax[a] == tn) {
+        b[a] = min(max(b[a] + step[a], 0), pg.odim[a] - 1);
+        tmax[a] += tdel[a];
+      }
+    }
+  }
+  return false;
 }
 
 // Extinction and albedo at q from brick b (trilinear sample, TF lookup).
@@ -241,7 +297,6 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
   bool ha = false, hb = false;
   if (i < n_in) {
     PRay r = in[i];
-    const float inv_sbar = 1.f / pg.sbar;
     if (r.meta & kShadowRay) {
       const int slot = (int)((r.meta >> 16) & 0xff);
       for (int it = 0;; ++it) {
@@ -252,10 +307,9 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
         }
         if (!(r.meta & kPendingEvent)) {
           const uint4 q = philox(r.pid, r.e, 1u, r.meta & 0xffffu, pg.seed, kPathKey1);
-          const float s = -logf(u01(q.x)) / pg.sbar;
-          r.b += s;
+          float s;
           ++st;
-          if (r.b >= r.c) {
+          if (!flight(sc, pg, r.x, r.w, -logf(u01(q.x)), s)) {
             add_contrib(pg, r.pid, slot, r.t[0] * r.a, r.t[1] * r.a, r.t[2] * r.a);
             break;
           }
@@ -273,7 +327,8 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
         }
         float sigma = 0.f, alb[3];
         if (owner >= 0) medium<T, WIDE>(sc, pg.bricks[owner], tfb, tfs, r.x, sigma, alb);
-        r.a *= 1.f - sigma * inv_sbar;
+        const float sbq = sbar_at(sc, pg, r.x);
+        if (sbq > 0.f) r.a *= 1.f - sigma / sbq;
         r.meta = (r.meta & ~(kPendingEvent | 0xffffu)) | (((r.meta & 0xffffu) + 1u) & 0xffffu);
         if (r.a == 0.f) break;  // nothing more can reach the light (the slot stays 0)
       }
@@ -286,8 +341,8 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
         }
         if (!(r.meta & kPendingEvent)) {
           const uint4 q = philox(r.pid, r.e, 0u, 0u, pg.seed, kPathKey1);
-          const float t = -logf(u01(q.x)) / pg.sbar;
-          if (t >= exit_dist(pg, r.x, r.w)) {  // leaves the volume
+          float t;
+          if (!flight(sc, pg, r.x, r.w, -logf(u01(q.x)), t)) {  // leaves the volume
             add_contrib(pg, r.pid, pg.B, r.t[0] * pg.Le[0], r.t[1] * pg.Le[1], r.t[2] * pg.Le[2]);
             break;
           }
@@ -311,7 +366,8 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
         if (owner >= 0) medium<T, WIDE>(sc, pg.bricks[owner], tfb, tfs, r.x, sigma, alb);
         r.meta &= ~kPendingEvent;
         const uint32_t e = r.e++;
-        if (r.a < sigma / pg.sbar) {  // real collision
+        const float sbq = sbar_at(sc, pg, r.x);
+        if (sbq > 0.f && r.a < sigma / sbq) {  // real collision
           const int k = (int)((r.meta >> 16) & 0xff);
 #pragma unroll
           for (int a = 0; a < 3; ++a) r.t[a] *= alb[a];
@@ -323,8 +379,6 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
             s.t[a] = r.t[a] * pg.Ll[a];
           }
           s.a = 1.f;
-          s.b = 0.f;
-          s.c = exit_dist(pg, r.x, pg.l);
           s.pid = r.pid;
           s.e = e;
           s.meta = kShadowRay | ((uint32_t)k << 16);
@@ -377,6 +431,94 @@ __global__ __launch_bounds__(256) void path_resolve_kernel(PathG pg, int n_pixel
   out_depth[p] = INFINITY;
 }
 
+// ---- majorant grid: value range and TF majorant per 16^3-cell block of the
+// global grid, over voxels [16 k - 1, 16 k + 16] per axis.  Every brick reduces
+// its owned voxels in each block window it meets; the ranges meet through
+// order-preserving integer atomics (so the grid does not depend on the bricking).
+__device__ __forceinline__ uint32_t ord_of(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_of(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+struct BlkRangeJob {
+  const void* vox;  // linear stored copy, x fastest
+  int s0[3];        // global voxel of stored element 0
+  int sdim[3];
+  int olo[3], ohi[3];  // owned voxels [olo, ohi)
+  int k0[3], kn[3];    // blocks whose window meets the owned voxels
+  int odim[3];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void block_range_kernel(BlkRangeJob J, uint32_t* __restrict__ lo_enc,
+                                                          uint32_t* __restrict__ hi_enc) {
+  __shared__ float red[2][4];
+  const int bid = blockIdx.x;
+  const int k[3] = {J.k0[0] + bid % J.kn[0], J.k0[1] + (bid / J.kn[0]) % J.kn[1],
+                    J.k0[2] + bid / (J.kn[0] * J.kn[1])};
+  int a0[3], n[3];
+  bool empty = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    a0[a] = max((k[a] << kOwnerShift) - 1, J.olo[a]);
+    const int a1 = min((k[a] << kOwnerShift) + (1 << kOwnerShift), J.ohi[a] - 1);
+    n[a] = a1 - a0[a] + 1;
+    empty |= n[a] <= 0;
+  }
+  if (empty) return;  // uniform over the workgroup
+  const T* vox = (const T*)J.vox;
+  float mn = INFINITY, mx = -INFINITY;
+  const int total = n[0] * n[1] * n[2];
+  for (int i = threadIdx.x; i < total; i += 256) {
+    const int x = a0[0] + i % n[0], y = a0[1] + (i / n[0]) % n[1], z = a0[2] + i / (n[0] * n[1]);
+    const size_t off = ((size_t)(z - J.s0[2]) * J.sdim[1] + (y - J.s0[1])) * J.sdim[0] + (x - J.s0[0]);
+    float v;
+    if constexpr (sizeof(T) == 2)
+      v = __half2float(vox[off]);
+    else
+      v = vox[off];
+    mn = fminf(mn, v);
+    mx = fmaxf(mx, v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, o));
+    mx = fmaxf(mx, __shfl_xor(mx, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = mn;
+    red[1][threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int wv = 1; wv < 4; ++wv) {
+      mn = fminf(mn, red[0][wv]);
+      mx = fmaxf(mx, red[1][wv]);
+    }
+    const size_t idx = ((size_t)k[2] * J.odim[1] + k[1]) * J.odim[0] + k[0];
+    atomicMin(lo_enc + idx, ord_of(mn));
+    atomicMax(hi_enc + idx, ord_of(mx));
+  }
+}
+
+__global__ __launch_bounds__(256) void block_majorant_kernel(const uint32_t* __restrict__ lo_enc,
+                                                             const uint32_t* __restrict__ hi_enc, int n,
+                                                             const float4* __restrict__ tf, int ntf, float tf_lo,
+                                                             float tf_hi, float density, float* __restrict__ sgrid) {
+  __shared__ float alpha[kMaxTF];
+  for (int i = threadIdx.x; i < ntf; i += 256) alpha[i] = tf[i].w;
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t lo = lo_enc[i];
+  float m = 0.f;  // a block no brick reached (a gap) is empty
+  if (lo != 0xffffffffu) m = tf_majorant(make_float2(float_of(lo), float_of(hi_enc[i])), alpha, ntf, tf_lo, tf_hi);
+  sgrid[i] = density * m;
+}
+
 struct PathState {
   PRay* pool[2] = {nullptr, nullptr};
   size_t cap = 0;  // records per pool
@@ -386,6 +528,12 @@ struct PathState {
   int brick_cap = 0;
   int16_t* d_owner = nullptr;
   size_t owner_cap = 0;
+  uint32_t* d_lo = nullptr;  // encoded block ranges
+  uint32_t* d_hi = nullptr;
+  float* d_sgrid = nullptr;
+  size_t grid_cap = 0;
+  uint64_t grid_commit = ~0ull, grid_tf = ~0ull;
+  size_t grid_n = 0;
   uint64_t owner_version = 0;
   int odim[3] = {0, 0, 0};
   int* d_count = nullptr;  // [0], [1]: sizes of the two pools
@@ -400,6 +548,9 @@ void path_state_free(PathState* p) {
   dev_free(p->contrib);
   dev_free(p->d_bricks);
   dev_free(p->d_owner);
+  dev_free(p->d_lo);
+  dev_free(p->d_hi);
+  dev_free(p->d_sgrid);
   dev_free(p->d_count);
   dev_free(p->d_stats);
   if (p->h_count) (void)hipHostFree(p->h_count);
@@ -542,8 +693,60 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
     DPR_HIP(hipStreamSynchronize(st));
     for (const auto& v : tfh) amax = std::max(amax, v.w);
   }
+  // majorant grid, rebuilt after a commit or a TF change
+  if (ps->grid_commit != w->commit_version || ps->grid_tf != w->tf_version || ps->grid_n != n_own) {
+    if (n_own > ps->grid_cap) {
+      DPR_HIP(hipStreamSynchronize(st));
+      dev_free(ps->d_lo);
+      dev_free(ps->d_hi);
+      dev_free(ps->d_sgrid);
+      ps->d_lo = ps->d_hi = nullptr;
+      ps->d_sgrid = nullptr;
+      ps->grid_cap = 0;
+      if ((s = dev_alloc((void**)&ps->d_lo, n_own * sizeof(uint32_t), "block ranges")) != DPR_OK) return s;
+      if ((s = dev_alloc((void**)&ps->d_hi, n_own * sizeof(uint32_t), "block ranges")) != DPR_OK) return s;
+      if ((s = dev_alloc((void**)&ps->d_sgrid, n_own * sizeof(float), "block majorants")) != DPR_OK) return s;
+      ps->grid_cap = n_own;
+    }
+    DPR_HIP(hipMemsetAsync(ps->d_lo, 0xff, n_own * sizeof(uint32_t), st));
+    DPR_HIP(hipMemsetAsync(ps->d_hi, 0, n_own * sizeof(uint32_t), st));
+    for (const auto& b : w->bricks) {
+      BlkRangeJob J{};
+      J.vox = b.linear;
+      int blocks = 1;
+      for (int a = 0; a < 3; ++a) {
+        J.s0[a] = (int)(b.olo[a] - b.glo[a]);
+        J.sdim[a] = b.sdim[a];
+        J.olo[a] = (int)b.olo[a];
+        J.ohi[a] = (int)b.ohi[a];
+        // window [16 k - 1, 16 k + 16] meets [olo, ohi - 1]
+        const int k0 = J.olo[a] >= 16 ? (J.olo[a] - 16 + 15) / 16 : 0;
+        const int k1 = std::min(J.ohi[a] / 16, od[a] - 1);
+        J.k0[a] = k0;
+        J.kn[a] = std::max(0, k1 - k0 + 1);
+        J.odim[a] = od[a];
+        blocks *= J.kn[a];
+      }
+      if (blocks == 0) continue;
+      if (b.dtype == DPR_F16)
+        hipLaunchKernelGGL(block_range_kernel<__half>, dim3((unsigned)blocks), dim3(256), 0, st, J, ps->d_lo,
+                           ps->d_hi);
+      else
+        hipLaunchKernelGGL(block_range_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, J, ps->d_lo,
+                           ps->d_hi);
+      DPR_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(block_majorant_kernel, dim3((unsigned)((n_own + 255) / 256)), dim3(256), 0, st, ps->d_lo,
+                       ps->d_hi, (int)n_own, w->tf_dev, w->ntf, w->tf_lo, w->tf_hi, w->density, ps->d_sgrid);
+    DPR_HIP(hipGetLastError());
+    ps->grid_commit = w->commit_version;
+    ps->grid_tf = w->tf_version;
+    ps->grid_n = n_own;
+  }
+
   PathG pg{};
   pg.bricks = ps->d_bricks;
+  pg.sgrid = ps->d_sgrid;
   pg.nbricks = K;
   pg.owner = ps->d_owner;
   for (int a = 0; a < 3; ++a) pg.odim[a] = od[a];

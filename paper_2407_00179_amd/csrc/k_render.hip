@@ -6,6 +6,7 @@
 
 #include "device_common.h"
 #include "kernels.h"
+#include "majorant.h"
 #include "march.h"
 
 namespace dpr {
@@ -165,18 +166,8 @@ __global__ __launch_bounds__(256) void majorant_kernel(MajJobs jobs, const float
   int j = 0;
   while (j < jobs.n && m >= jobs.count[j]) m -= jobs.count[j++];
   if (j >= jobs.n) return;
-  float2 r = jobs.ranges[j][m];
-  float span = tf_hi - tf_lo;
-  float ua = (r.x - tf_lo) / span;
-  float ub = (r.y - tf_lo) / span;
-  ua = fminf(fmaxf(ua, 0.f), 1.f);
-  ub = fminf(fmaxf(ub, 0.f), 1.f);
-  float xa = ua * (float)(ntf - 1);
-  float xb = ub * (float)(ntf - 1);
-  int e0 = max((int)floorf(xa) - 1, 0);
-  int e1 = min((int)ceilf(xb) + 1, ntf - 1);
-  float a = 0.f;
-  for (int e = e0; e <= e1; ++e) a = fmaxf(a, alpha[e]);
+  const float2 r = jobs.ranges[j][m];
+  float a = tf_majorant(r, alpha, ntf, tf_lo, tf_hi);
   if (jobs.iso_on && a == 0.f) {
     // a margin of 1e-6 of the range's magnitude covers the rounding of FP32
     // trilinear values (a few ulps); no contraction, so the class is exact

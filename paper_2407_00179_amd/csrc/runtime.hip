@@ -544,6 +544,7 @@ dpr_status dpr_world_commit(dpr_world w) {
   // (stream-ordered: later renders on the device stream see the new data; the
   // host does not wait)
   w->committed = true;
+  ++w->commit_version;
   return DPR_OK;
 }
 

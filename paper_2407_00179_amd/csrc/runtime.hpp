@@ -128,6 +128,7 @@ struct dpr_world_t {
   dpr::BatchState* batch = nullptr;
   dpr::PathState* path = nullptr;
   uint64_t geo_version = 1;  // bumped when a brick is added (invalidates batch item lists)
+  uint64_t commit_version = 0;  // bumped by every commit (brick data may have changed)
   // pinned staging for transfer-function uploads; tf_ev marks the last upload
   float4* tf_host = nullptr;
   hipEvent_t tf_ev = nullptr;

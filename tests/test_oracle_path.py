@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from oracle import PathParams, RenderParams
-from oracle.path import _shadow, trace_paths
+from oracle.path import _block_of, _medium, _shadow, block_majorants, trace_paths
 from oracle.rng import philox4x32, uniforms
 from synth import Camera
 
@@ -187,14 +187,35 @@ def test_ratio_tracking_transmittance_is_unbiased():
     x0 = 0.1 * dims[0] * h
     y0 = np.tile([x0, 4 * h, 4 * h], (n, 1))
     l = np.array([1.0, 0.0, 0.0])
-    sbar = D * tf[:, 3].max()
+    prm = RenderParams(0.5, 1.0, D)
     margin = np.full(n, np.inf)
-    T = _shadow(vol, dims, tf, RenderParams(0.5, 1.0, D), y0, l, np.arange(n), np.zeros(n, dtype=np.int64), 5,
-                sbar, box_hi, margin, np.arange(n))
+    T = _shadow(vol, dims, tf, prm, y0, l, np.arange(n), np.zeros(n, dtype=np.int64), 5,
+                block_majorants(vol, dims, tf, prm), margin, np.arange(n))
     want = math.exp(-_optical_depth_along_x(dims, D, x0, dims[0] * h))
     se = T.std() / math.sqrt(n)
     assert abs(T.mean() - want) < 4 * se, (T.mean(), want, se)
     assert np.all((T >= 0) & (T <= 1))
+
+
+def test_block_majorants_bound_sigma():
+    """Every point's extinction lies under its block's majorant, and a block of
+    majorant 0 is exactly transparent (the apron of C13 covers the trilinear
+    support of every point whose cell is in the block)."""
+    dims = (40, 36, 30)
+    z, y, x = np.mgrid[0:30, 0:36, 0:40]
+    vol = np.exp(-((x - 8.0) ** 2 + (y - 9.0) ** 2 + (z - 7.0) ** 2) / 60.0)
+    vol = vol + 0.05 * np.random.default_rng(3).random(vol.shape)
+    tf = _tf((1.0, 1.0, 1.0), 0.0)
+    tf[:, 3] = np.where(np.arange(256) > 150, np.linspace(0.0, 1.0, 256), 0.0)
+    prm = RenderParams(0.5, 1.0, 7.0)
+    grid = block_majorants(vol, dims, tf, prm)
+    assert grid.shape == (2, 3, 3) and np.any(grid == 0.0) and np.any(grid > 0.0)
+    h = 1.0 / max(dims)
+    q = np.random.default_rng(4).random((50000, 3)) * np.array(dims) * h
+    sigma, _ = _medium(vol, dims, tf, prm, q)
+    b = _block_of(q, dims, h)
+    sb = grid[b[:, 2], b[:, 1], b[:, 0]]
+    assert np.all(sigma <= sb * (1 + 1e-12)) and np.all(sigma[sb == 0.0] == 0.0)
 
 
 def test_paths_are_reproducible_and_keyed_by_pixel():
