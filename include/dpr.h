@@ -292,8 +292,10 @@ dpr_status dpr_composite_deep(dpr_device, const dpr_deep_frame* parts, int32_t k
  * and a ray whose next tentative collision lies in another brick is handed to
  * that brick for the next wave.
  * Estimator: extinction D * A(v) (the TF opacity), single-scattering albedo =
- * the TF's RGB, isotropic phase; delta tracking under one constant majorant
- * (D * max A over the table, so the image does not depend on the bricking);
+ * the TF's RGB, isotropic phase; delta tracking under a piecewise-constant
+ * majorant on the global grid of 16^3-cell blocks (D times the TF majorant of
+ * the block's value range, walked with a 3D DDA; the grid is global, so the
+ * image does not depend on the bricking);
  * at each real collision a shadow ray towards the light estimates the
  * transmittance by ratio tracking and adds thr * light * T / (4 pi); a path
  * leaving the volume box adds thr * env; a path ends after max_bounces real

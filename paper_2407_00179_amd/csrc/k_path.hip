@@ -9,7 +9,8 @@
 // next pool with one atomic per wave.  A path's contributions land in fixed
 // slots and are summed in a fixed order, so the image does not depend on the
 // order of rays in the pools, nor on the bricking: the tentative collisions come
-// from one constant majorant and a counter-based generator keyed by the path.
+// from majorants on a grid of the whole volume and a counter-based generator
+// keyed by the path.
 //
 // Estimator (per path): delta tracking under a piecewise-constant majorant on the
 // global grid of 16^3-cell blocks (D times the TF majorant of the block's value
@@ -56,7 +57,7 @@ struct PathG {
   const int16_t* owner;
   int odim[3];              // blocks per axis (owner table and majorant grid)
   const float* sgrid;       // majorant per block: D * TF majorant of its value range
-  float sbar;               // D * max TF opacity (0: nothing can collide)
+  float sbar;               // D * max TF opacity; only tells vacuum (0) from not
   float box[3];
   float l[3];   // unit direction towards the light
   float Ll[3];  // light radiance / (4 pi)

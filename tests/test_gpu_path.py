@@ -76,9 +76,9 @@ def test_paths_match_oracle(gpu_lib, dpr, dtype):
 
 
 def test_bricking_does_not_change_a_bit(gpu_lib, dpr):
-    """The tentative collisions come from the path's own random numbers and one
-    constant majorant, so any bricking gives the same bits; forwarding shows in
-    the counters only."""
+    """The tentative collisions come from the path's own random numbers and the
+    majorants of a grid over the whole volume, so any bricking gives the same
+    bits; forwarding shows in the counters only."""
     dims = (48, 44, 40)
     vol = _volume(dims, 21)
     tf = _tf(3002)
