@@ -303,7 +303,8 @@ dpr_status dpr_composite_deep(dpr_device, const dpr_deep_frame* parts, int32_t k
  * (seed, 0x243F6A88) and counter (path id, event, 0 for the path / 1 for its
  * shadow ray, step), uniform ((x >> 9) + 1/2) 2^-23; path id =
  * (row * width + column) * spp + sample.  Camera rays pass through pixel
- * centres.  Gaps between bricks are empty space.                              */
+ * centres, and a camera path starts in the brick of its first tentative
+ * collision (no hand-over counted).  Gaps between bricks are empty space.       */
 typedef struct {
   float light_dir[3];    /* direction the light travels (any length > 0)          */
   float light_rgb[3];    /* radiance of the directional light, >= 0                */

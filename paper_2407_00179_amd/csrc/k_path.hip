@@ -243,7 +243,10 @@ __device__ __forceinline__ void wave_stats(const PathG& pg, unsigned ev, unsigne
   }
 }
 
-// Camera paths: one per (pixel, sample), started at the volume box entry.
+// Camera paths: one per (pixel, sample), started at the volume box entry with no
+// brick.  The first flight needs only the majorant grid, which every rank holds,
+// so the brick of the first tentative collision starts the path without a
+// hand-over.
 __global__ __launch_bounds__(256) void path_init_kernel(PathG pg, CamG cam, int W, int H) {
   const long long total = (long long)W * H * pg.spp;
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -356,11 +359,14 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
         }
         const int owner = locate(sc, pg, r.x, r.brick);
         if (owner >= 0 && owner != r.brick) {
-          r.brick = owner;
-          ra = r;
-          ha = true;
-          ++fw;
-          break;
+          if (r.brick >= 0) {
+            r.brick = owner;
+            ra = r;
+            ha = true;
+            ++fw;
+            break;
+          }
+          r.brick = owner;  // a camera path starts with the brick of its first tentative collision
         }
         ++ev;
         float sigma = 0.f, alb[3] = {0.f, 0.f, 0.f};

@@ -90,6 +90,7 @@ def test_bricking_does_not_change_a_bit(gpu_lib, dpr):
         got, _, st = _gpu(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, 4, 2, 17)
         log(f"  {len(boxes)} bricks: {st}")
         outs.append((got, st))
+    assert outs[0][1]["forwards"] == 0  # one brick: nothing to hand over
     for got, st in outs[1:]:
         assert np.array_equal(got, outs[0][0])
         assert st["events"] == outs[0][1]["events"] and st["shadow_steps"] == outs[0][1]["shadow_steps"]
