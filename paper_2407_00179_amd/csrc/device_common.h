@@ -22,7 +22,7 @@ struct CamG {
 
 // One brick as the kernels see it.
 struct BrickG {
-  const void* data;       // 8^3-blocked voxels (x fastest inside a block, blocks x-fastest)
+  const void* data;       // 8^3-blocked voxels (interleaved order inside a block, blocks x-fastest)
   int slo[3];             // global voxel index of stored voxel (0,0,0)
   int sdim[3];            // stored dims
   uint32_t bsy, bsz;      // element stride of one block row in y / one block slab in z
@@ -44,9 +44,21 @@ struct SceneG {
   float iso, iso_ka, iso_kd;
 };
 
-__device__ __forceinline__ uint32_t blk_x(int i) { return ((uint32_t)(i >> 3) << 9) + (uint32_t)(i & 7); }
-__device__ __forceinline__ uint32_t blk_y(int j, uint32_t bsy) { return (uint32_t)(j >> 3) * bsy + (uint32_t)((j & 7) << 3); }
-__device__ __forceinline__ uint32_t blk_z(int k, uint32_t bsz) { return (uint32_t)(k >> 3) * bsz + (uint32_t)((k & 7) << 6); }
+// Inside an 8^3 block the 9 bits of a voxel's index interleave its coordinates:
+// bits 0-1 x&3, bit 2 y&1, bit 3 z&1, bit 4 (y>>1)&1, bit 5 (z>>1)&1, bit 6
+// (x>>2)&1, bit 7 (y>>2)&1, bit 8 (z>>2)&1.  Every 16 consecutive voxels form a
+// 4x2x2 brick, every 32 a 4x4x2 one and every 64 a 4x4x4 one, so the 8 voxels
+// around a sample span fewer cache lines than with whole x rows, whatever the
+// ray's direction; the index stays a sum of one term per axis.
+__device__ __forceinline__ uint32_t blk_x(int i) {
+  return ((uint32_t)(i >> 3) << 9) + (uint32_t)(i & 3) + ((uint32_t)(i & 4) << 4);
+}
+__device__ __forceinline__ uint32_t blk_y(int j, uint32_t bsy) {
+  return (uint32_t)(j >> 3) * bsy + ((uint32_t)(j & 1) << 2) + ((uint32_t)(j & 2) << 3) + ((uint32_t)(j & 4) << 5);
+}
+__device__ __forceinline__ uint32_t blk_z(int k, uint32_t bsz) {
+  return (uint32_t)(k >> 3) * bsz + ((uint32_t)(k & 1) << 3) + ((uint32_t)(k & 2) << 4) + ((uint32_t)(k & 4) << 6);
+}
 
 // Byte offsets of the same layout for elements of 1 << SH bytes (bsy_b, bsz_b:
 // byte strides), for bricks whose blocked array is below 4 GiB: a voxel is then
@@ -54,15 +66,15 @@ __device__ __forceinline__ uint32_t blk_z(int k, uint32_t bsz) { return (uint32_
 // vector offset, with no per-lane 64-bit address arithmetic.
 template <int SH>
 __device__ __forceinline__ uint32_t blkb_x(int i) {
-  return ((uint32_t)(i >> 3) << (9 + SH)) + ((uint32_t)(i & 7) << SH);
+  return ((uint32_t)(i >> 3) << (9 + SH)) + (blk_x(i & 7) << SH);
 }
 template <int SH>
 __device__ __forceinline__ uint32_t blkb_y(int j, uint32_t bsy_b) {
-  return (uint32_t)(j >> 3) * bsy_b + ((uint32_t)(j & 7) << (3 + SH));
+  return (uint32_t)(j >> 3) * bsy_b + (blk_y(j & 7, 0u) << SH);
 }
 template <int SH>
 __device__ __forceinline__ uint32_t blkb_z(int k, uint32_t bsz_b) {
-  return (uint32_t)(k >> 3) * bsz_b + ((uint32_t)(k & 7) << (6 + SH));
+  return (uint32_t)(k >> 3) * bsz_b + (blk_z(k & 7, 0u) << SH);
 }
 template <typename T>
 __device__ __forceinline__ float load_voxel_b(const void* base, uint32_t boff) {

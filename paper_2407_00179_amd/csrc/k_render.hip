@@ -12,24 +12,25 @@
 namespace dpr {
 
 // ------------------------------------------------------------------ relayout
-// Linear x-fastest stored brick -> 8^3 blocks (x fastest inside a block, blocks
-// x-fastest).  Inside a block x is fastest, so the 8 voxels of one block row are
-// contiguous in both layouts and the re-tiling is a copy of aligned 4-voxel runs,
-// no transpose: a workgroup covers 64 x-voxels of 16 rows (y) of one z-slice, a
-// wave 4 consecutive rows, so its reads are 4 contiguous row segments and, per
-// block, its writes are the 4 rows' runs back to back (a whole 128-byte line in
-// FP32).  Padding voxels (beyond the stored dims) are zeroed at allocation and
-// never read by the sampler.
+// Linear x-fastest stored brick -> 8^3 blocks (blocks x-fastest; the voxel order
+// inside a block is the one of blk_x/blk_y/blk_z).  Four consecutive x-voxels from
+// a multiple of 4 stay contiguous in both layouts, so the re-tiling is a copy of
+// aligned 4-voxel runs, no transpose: a workgroup covers 64 x-voxels of 8 rows (y)
+// in 2 z-slices, a wave a (y, y+1) x (z, z+1) pair of row pairs, so its reads are
+// 4 contiguous row segments and, per block, its writes fill whole 64-byte
+// sectors (4x2x2 voxels in FP32).  Padding voxels (beyond the stored dims) are
+// zeroed at allocation and never read by the sampler.
 template <typename E, typename V4>
 __global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src, E* __restrict__ dst, int sx,
-                                                       int sy, uint32_t bsy, uint32_t bsz, int nxt, int nyt) {
+                                                       int sy, int sz, uint32_t bsy, uint32_t bsz, int nxt,
+                                                       int nyt) {
   const int t = threadIdx.x;
-  const int q = t & 15, yy = t >> 4;  // 16 four-voxel runs x 16 rows
+  const int q = t & 15, r = t >> 4;  // 16 four-voxel runs x 16 (y, z) rows
   const int bxi = blockIdx.x % nxt;
   const int rest = blockIdx.x / nxt;
-  const int yb = rest % nyt, z = rest / nyt;
-  const int x0 = bxi * 64 + 4 * q, y = yb * 16 + yy;
-  if (x0 >= sx || y >= sy) return;
+  const int yb = rest % nyt, zb = rest / nyt;
+  const int x0 = bxi * 64 + 4 * q, y = yb * 8 + 2 * (r >> 2) + (r & 1), z = zb * 2 + ((r >> 1) & 1);
+  if (x0 >= sx || y >= sy || z >= sz) return;
   const E* s = src + ((size_t)z * sy + y) * sx + x0;
   E* d = dst + ((size_t)blk_z(z, bsz) + blk_y(y, bsy) + blk_x(x0));
   if (x0 + 4 <= sx) {
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(256) void relayout_kernel(const E* __restrict__ src
     v.y = s[1];
     v.z = s[2];
     v.w = s[3];
-    *(V4*)d = v;  // x0 is a multiple of 4: the run is aligned and inside one block row
+    *(V4*)d = v;  // x0 is a multiple of 4: the run is aligned and contiguous in the block
   } else {
     for (int i = 0; i < sx - x0; ++i) d[i] = s[i];
   }
@@ -223,15 +224,15 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
 hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
                            int bz, hipStream_t st) {
   (void)bz;
-  const int nxt = (sx + 63) / 64, nyt = (sy + 15) / 16;
+  const int nxt = (sx + 63) / 64, nyt = (sy + 7) / 8, nzt = (sz + 1) / 2;
   const uint32_t bsy = (uint32_t)kBlockVoxels * (uint32_t)bx, bsz = bsy * (uint32_t)by;
-  const dim3 grid((unsigned)nxt * nyt * sz);
+  const dim3 grid((unsigned)nxt * nyt * nzt);
   if (elem_bytes == 4)
     hipLaunchKernelGGL((relayout_kernel<uint32_t, uint4>), grid, dim3(256), 0, st, (const uint32_t*)src,
-                       (uint32_t*)dst, sx, sy, bsy, bsz, nxt, nyt);
+                       (uint32_t*)dst, sx, sy, sz, bsy, bsz, nxt, nyt);
   else
     hipLaunchKernelGGL((relayout_kernel<uint16_t, ushort4>), grid, dim3(256), 0, st, (const uint16_t*)src,
-                       (uint16_t*)dst, sx, sy, bsy, bsz, nxt, nyt);
+                       (uint16_t*)dst, sx, sy, sz, bsy, bsz, nxt, nyt);
   return hipGetLastError();
 }
 
