@@ -4,7 +4,7 @@
 Default workload (one "step" = the whole hot path once): a 512^3 FP32 blob+noise
 volume split into 2x2x2 bricks of 256^3 owned cells with one ghost layer
 (257^3 stored), rendered at 1024x1024 through one camera:
-  commit (8^3 relayout of every brick + macrocell min/max ranges)
+  commit (8^3-blocked copy of every brick + macrocell min/max ranges, one pass)
   -> transfer-function majorants
   -> 8 per-brick emission-absorption ray marches (partial RGBA+depth frames)
   -> sort-last composite of the 8 partial frames.
@@ -135,7 +135,7 @@ def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
     w.set_batch_tile(*tile)
 
     def step():
-        w.commit()                                        # relayout + macrocell ranges
+        w.commit()                                        # blocked copies + macrocell ranges
         w.set_transfer_function(tf, 0.0, 1.0, cfg.density)  # majorants follow
         w.render_frame(out)                               # batched march + tile composite
 
@@ -589,7 +589,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, "
-                               "step 0.5 voxel, ERT 0.99, 16^3 macrocells; per step: commit (relayout + "
+                               "step 0.5 voxel, ERT 0.99, 16^3 macrocells; per step: commit (blocked copies + "
                                "macrocell ranges), majorants, batched march of the 8 bricks, tile composite",
                    "logical_samples_per_step": r["samples"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",

@@ -7,17 +7,17 @@
 
 namespace dpr {
 
-hipError_t launch_relayout(const void* src, void* dst, int elem_bytes, int sx, int sy, int sz, int bx, int by,
-                           int bz, hipStream_t st);
-// Macrocell ranges of several bricks (linear stored copy, device view, output):
-// one launch per element type and column count.
+// One brick of a commit: its linear stored copy, device view (view.data: the
+// blocked copy to fill) and macrocell ranges to fill.
 struct McBrick {
   const void* linear;
   BrickG view;
   float2* ranges;
   bool f16;
 };
-hipError_t launch_macrocells(const McBrick* bricks, int n, int mc, hipStream_t st);
+// Blocked copy and macrocell ranges of several bricks in one pass over their
+// linear stored copies.
+hipError_t launch_commit(const McBrick* bricks, int n, int mc, hipStream_t st);
 // Majorants of up to kMajJobs bricks in one launch (passed by value).
 constexpr int kMajJobs = 32;
 struct MajJobs {

@@ -516,11 +516,9 @@ dpr_status dpr_world_commit(dpr_world w) {
       size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.elem();
       st = dev_alloc(&b.blocked, bytes, "blocked brick");
       if (st != DPR_OK) return st;
-      // padding voxels (beyond the stored dims) are never written by the relayout
+      // padding voxels (beyond the stored dims) are never written by the commit
       DPR_HIP(hipMemsetAsync(b.blocked, 0, bytes, w->dev->stream));
     }
-    DPR_HIP(launch_relayout(b.linear, b.blocked, (int)b.elem(), b.sdim[0], b.sdim[1], b.sdim[2], b.bdim[0],
-                            b.bdim[1], b.bdim[2], w->dev->stream));
     int md[3];
     for (int a = 0; a < 3; ++a) md[a] = (int)((b.ohi[a] - b.olo[a] + mc - 1) / mc);
     if (!b.ranges || b.mc != mc || md[0] != b.mdim[0] || md[1] != b.mdim[1] || md[2] != b.mdim[2]) {
@@ -540,7 +538,7 @@ dpr_status dpr_world_commit(dpr_world w) {
   }
   std::vector<McBrick> mcb;
   for (auto& b : w->bricks) mcb.push_back({b.linear, b.device_view(false), b.ranges, b.dtype == DPR_F16});
-  DPR_HIP(launch_macrocells(mcb.data(), (int)mcb.size(), mc, w->dev->stream));
+  DPR_HIP(launch_commit(mcb.data(), (int)mcb.size(), mc, w->dev->stream));
   // (stream-ordered: later renders on the device stream see the new data; the
   // host does not wait)
   w->committed = true;
