@@ -54,10 +54,10 @@ OPS_PER_SAMPLE = 60
 #     from a plain 256 MiB device-to-device copy in the same runs);
 #   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
 MARCH_COUNTERS = {
-    "sources_sha256": "f0dd26a82611f86f3c3360970b7a5d02f7dd63a160aa8339eb885f64c947d825",
-    "traffic_bytes_per_launch": 350576902,
-    "fetch_kib": 160542, "write_kib": 21327, "fetch_scale": 1.9997, "write_scale": 1.0,
-    "valu_lane_instr_per_sample": 61.5,
+    "sources_sha256": "6f9d23dc49fd83faf54d8c9f9f1eb7a429441a5ae22cf4d5b9512c3ba516119b",
+    "traffic_bytes_per_launch": 306019175,
+    "fetch_kib": 139291, "write_kib": 20310, "fetch_scale": 1.9997, "write_scale": 1.0,
+    "valu_lane_instr_per_sample": 69.1,
 }
 
 

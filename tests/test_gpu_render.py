@@ -156,6 +156,35 @@ def test_macrocells_and_majorants_bitwise(gpu_lib, dpr):
         w.release()
 
 
+@pytest.mark.parametrize("mc", [2, 64])
+def test_commit_extreme_macrocell_edges(gpu_lib, dpr, mc):
+    """The one-pass commit (blocked copy + ranges) at the smallest and largest
+    macrocell edge, with ghost layers of 1 and 3 voxels (0 on volume faces): the
+    ranges are the oracle's and every partial frame matches the oracle's."""
+    dims = (45, 38, 29)
+    vol, tf = _small_case(dims, seed=41, nb=4)
+    prm = RenderParams(0.5, 1.0, 25.0)
+    cam = orbit_camera(dims, 24, 20)
+    boxes = kd_split(dims, 4, seed=5, max_ratio=4.0)
+    py, px = np.mgrid[0:cam.height, 0:cam.width]
+    px, py = px.ravel(), py.ravel()
+    for ghost in (1, 3):
+        log(f"mc {mc} ghost {ghost}")
+        w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=mc, ghost=ghost)
+        for i, (lo, hi) in enumerate(boxes):
+            b = extract_brick(vol, dims, lo, hi, ghost)
+            got_r, _ = w.macrocells(i)
+            assert np.array_equal(got_r, oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, mc)), (ghost, i)
+            fr = dpr.Frame(gpu_lib, cam.width, cam.height, counts=True)
+            w.render_partial(i, fr)
+            rgba, depth, n = frame_np(fr)
+            check_bracketed(rgba, depth, n,
+                            lambda th: oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, th, ghost=ghost),
+                            1.0, TOL_F32, f"mc {mc} ghost {ghost} brick {i}")
+            fr.release()
+        w.release()
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float16])
 def test_ghost_width_does_not_change_a_bit(gpu_lib, dpr, dtype):
     """Ghost layers of 1, 2 or 3 voxels give the same frames, and each its oracle
