@@ -132,7 +132,9 @@ dpr_status dpr_world_add_brick(dpr_world, const void* voxels, dpr_dtype dtype, i
  * (samples fall up to half a step, at most half a voxel, outside the owned
  * box, and trilinear reads one voxel beyond that).  Then
  * each brick is re-tiled into 8^3-voxel blocks and its macrocell min/max
- * ranges are built (window [mc*m - 1, mc*m + mc] of owned-relative voxels).
+ * ranges are built (window [mc*m - 1, mc*m + mc] of owned-relative voxels), both
+ * in one pass over the brick's linear copy; stream-ordered, the host does not
+ * wait.
  * Gaps between bricks are allowed and render empty.                             */
 dpr_status dpr_world_commit(dpr_world);
 
