@@ -86,6 +86,17 @@ __device__ __forceinline__ float load_voxel_b(const void* base, uint32_t boff) {
     return *(const float __attribute__((address_space(1)))*)q;
 }
 
+// An F32 voxel at byte offset boff and the element after it in memory, in one
+// load aligned to 4 bytes only.  A blocked array carries kPairSlack spare bytes so
+// the element after its last voxel can be read.
+constexpr size_t kPairSlack = 64;
+__device__ __forceinline__ float2 load_pair_f32(const void* base, uint32_t boff) {
+  typedef float F2 __attribute__((ext_vector_type(2), aligned(4)));
+  using GC = const char __attribute__((address_space(1)))*;
+  const F2 f = *(const F2 __attribute__((address_space(1)))*)((GC)base + boff);
+  return make_float2(f.x, f.y);
+}
+
 template <typename T> __device__ __forceinline__ float load_voxel(const T* p, uint32_t off);
 template <> __device__ __forceinline__ float load_voxel<float>(const float* p, uint32_t off) { return p[off]; }
 template <> __device__ __forceinline__ float load_voxel<__half>(const __half* p, uint32_t off) {

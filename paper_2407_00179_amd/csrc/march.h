@@ -152,15 +152,40 @@ __device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const 
     const uint32_t x0 = blkb_x<SH>(lx), x1 = blkb_x<SH>(lx + 1);
     const uint32_t y0 = blkb_y<SH>(ly, bsy), y1 = blkb_y<SH>(ly + 1, bsy);
     const uint32_t z0 = blkb_z<SH>(lz, bsz), z1 = blkb_z<SH>(lz + 1, bsz);
-    const uint32_t a00 = x0 + y0, a10 = x1 + y0, a01 = x0 + y1, a11 = x1 + y1;
-    g.v[0] = load_voxel_b<T>(b.data, a00 + z0);
-    g.v[1] = load_voxel_b<T>(b.data, a10 + z0);
-    g.v[2] = load_voxel_b<T>(b.data, a01 + z0);
-    g.v[3] = load_voxel_b<T>(b.data, a11 + z0);
-    g.v[4] = load_voxel_b<T>(b.data, a00 + z1);
-    g.v[5] = load_voxel_b<T>(b.data, a10 + z1);
-    g.v[6] = load_voxel_b<T>(b.data, a01 + z1);
-    g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
+    if constexpr (sizeof(T) == 4) {
+      // voxel lx + 1 follows voxel lx in memory unless lx ends a 4-voxel x-run, so
+      // each x-pair is one 8-byte load; lanes at a run's end read lx + 1 on their
+      // own.  F16 keeps one load per voxel: a 4-byte pair load at 2-byte alignment,
+      // and an aligned 8-byte run load shifted to the pair, both measured slower.
+      const uint32_t a00 = x0 + y0, a01 = x0 + y1;
+      const float2 c0 = load_pair_f32(b.data, a00 + z0), c1 = load_pair_f32(b.data, a01 + z0);
+      const float2 c2 = load_pair_f32(b.data, a00 + z1), c3 = load_pair_f32(b.data, a01 + z1);
+      g.v[0] = c0.x;
+      g.v[1] = c0.y;
+      g.v[2] = c1.x;
+      g.v[3] = c1.y;
+      g.v[4] = c2.x;
+      g.v[5] = c2.y;
+      g.v[6] = c3.x;
+      g.v[7] = c3.y;
+      if ((lx & 3) == 3) {
+        const uint32_t a10 = x1 + y0, a11 = x1 + y1;
+        g.v[1] = load_voxel_b<T>(b.data, a10 + z0);
+        g.v[3] = load_voxel_b<T>(b.data, a11 + z0);
+        g.v[5] = load_voxel_b<T>(b.data, a10 + z1);
+        g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
+      }
+    } else {
+      const uint32_t a00 = x0 + y0, a10 = x1 + y0, a01 = x0 + y1, a11 = x1 + y1;
+      g.v[0] = load_voxel_b<T>(b.data, a00 + z0);
+      g.v[1] = load_voxel_b<T>(b.data, a10 + z0);
+      g.v[2] = load_voxel_b<T>(b.data, a01 + z0);
+      g.v[3] = load_voxel_b<T>(b.data, a11 + z0);
+      g.v[4] = load_voxel_b<T>(b.data, a00 + z1);
+      g.v[5] = load_voxel_b<T>(b.data, a10 + z1);
+      g.v[6] = load_voxel_b<T>(b.data, a01 + z1);
+      g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
+    }
   }
 }
 

@@ -513,7 +513,7 @@ dpr_status dpr_world_commit(dpr_world w) {
   const int mc = w->params.macrocell_cells;
   for (auto& b : w->bricks) {
     if (!b.blocked) {
-      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.elem();
+      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.elem() + kPairSlack;
       st = dev_alloc(&b.blocked, bytes, "blocked brick");
       if (st != DPR_OK) return st;
       // padding voxels (beyond the stored dims) are never written by the commit
