@@ -54,10 +54,10 @@ OPS_PER_SAMPLE = 60
 #     from a plain 256 MiB device-to-device copy in the same runs);
 #   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
 MARCH_COUNTERS = {
-    "sources_sha256": "6f9d23dc49fd83faf54d8c9f9f1eb7a429441a5ae22cf4d5b9512c3ba516119b",
-    "traffic_bytes_per_launch": 306019175,
-    "fetch_kib": 139291, "write_kib": 20310, "fetch_scale": 1.9997, "write_scale": 1.0,
-    "valu_lane_instr_per_sample": 69.1,
+    "sources_sha256": "b93bb3e868a14a2aa1bd1cfe55b367d98ea7898dea895af1e7396031ba807e70",
+    "traffic_bytes_per_launch": 329274235,
+    "fetch_kib": 152068, "write_kib": 17458, "fetch_scale": 1.9997, "write_scale": 1.0,
+    "valu_lane_instr_per_sample": 68.8,
 }
 
 
