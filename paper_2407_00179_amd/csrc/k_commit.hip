@@ -17,12 +17,12 @@
 #include <algorithm>
 #include <vector>
 
+#include "commit_span.h"
 #include "kernels.h"
 
 namespace dpr {
 
 constexpr int kCmWaves = 8;
-constexpr int kCmCols = 320;  // x-voxels a workgroup may load (5 chunks of 64)
 
 struct CmJob {
   const void* src;  // linear stored copy, x fastest
@@ -36,24 +36,6 @@ struct CmJobs {
   CmJob job[kCmJobs];
   int n;
 };
-
-// Window, write core and loaded range of macrocells [m0, m1) along one axis of
-// n stored voxels (align: 4 for x-runs, 2 for row pairs).
-struct AxisSpan {
-  int ws, we;  // window, inclusive
-  int cs, ce;  // write core, exclusive end
-  int ls, le;  // loaded, inclusive; ls a multiple of align
-};
-__host__ __device__ inline AxisSpan axis_span(int m0, int m1, int md, int mc, int g, int n, int align) {
-  AxisSpan a;
-  a.ws = std::max(0, mc * m0 - 1 + g);
-  a.we = std::min(n - 1, mc * m1 + g);
-  a.cs = m0 == 0 ? 0 : mc * m0 + g;
-  a.ce = m1 == md ? n : mc * m1 + g;
-  a.ls = std::min(a.ws, a.cs) & ~(align - 1);
-  a.le = std::min(n - 1, std::max(a.we, a.ce - 1) | (align - 1));
-  return a;
-}
 
 template <typename E>
 __device__ __forceinline__ float elem_value(E e) {
@@ -185,20 +167,6 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(8
   }
 }
 
-// Macrocells per workgroup along x: the most whose loaded x-range fits kCmCols.
-static int commit_per_chunk(const BrickG& b, int mc) {
-  const int sx = b.sdim[0], g = b.olo[0] - b.slo[0], md = b.mdim[0];
-  for (int pc = std::min(md, kCmCols / mc); pc > 1; --pc) {
-    bool fits = true;
-    for (int m0 = 0; m0 < md && fits; m0 += pc) {
-      const AxisSpan a = axis_span(m0, std::min(md, m0 + pc), md, mc, g, sx, 4);
-      fits = a.le - a.ls + 1 <= kCmCols;
-    }
-    if (fits) return pc;
-  }
-  return 1;
-}
-
 template <typename E, typename V4>
 static void launch_commit_t(const McBrick* bricks, const std::vector<int>& ids, int mc, hipStream_t st) {
   for (size_t i0 = 0; i0 < ids.size(); i0 += kCmJobs) {
@@ -222,7 +190,7 @@ static void launch_commit_t(const McBrick* bricks, const std::vector<int>& ids, 
       J.mdz = b.mdim[2];
       J.bsy = b.bsy;
       J.bsz = b.bsz;
-      J.per_chunk = commit_per_chunk(b, mc);
+      J.per_chunk = commit_per_chunk(b.sdim[0], b.olo[0] - b.slo[0], b.mdim[0], mc);
       J.chunks = (b.mdim[0] + J.per_chunk - 1) / J.per_chunk;
       J.blocks = J.chunks * b.mdim[1] * b.mdim[2];
       total += J.blocks;
