@@ -22,6 +22,8 @@
 
 namespace dpr {
 
+// Workgroups of 8 waves, held to 64 VGPRs (8 waves per SIMD) so that 4 of them
+// fit a CU: the 2048 windows of eight 256^3-owned bricks run in two full rounds.
 constexpr int kCmWaves = 8;
 
 struct CmJob {
