@@ -2,10 +2,10 @@
 //
 // Each brick plays one rank's part.  Rays (camera paths and their shadow rays)
 // live in a pool of 64-byte records and advance in waves: in a wave a ray is
-// worked on until it finishes, until its next tentative collision lies in
+// worked on until it finishes or until its next tentative collision lies in
 // another brick (it is then handed to that brick for the next wave: the
-// forwarding of rays between ranks), or until a real collision (the path and the
-// shadow ray it spawns both go to the next wave).  Records are appended to the
+// forwarding of rays between ranks); the shadow ray a real collision spawns goes
+// to the next wave while its path goes on.  Records are appended to the
 // next pool with one atomic per wave.  A path's contributions land in fixed
 // slots and are summed in a fixed order, so the image does not depend on the
 // order of rays in the pools, nor on the bricking: the tentative collisions come
@@ -68,6 +68,8 @@ struct PathG {
   float4* contrib;  // B + 1 slots per path: NEE at real collisions 0..B-1, environment at B
   PRay* out;
   int* out_count;
+  int* cursor_in;   // records of the input pool taken so far (this wave)
+  int* cursor_out;  // the same for the output pool: cleared for the next wave
   int out_cap;
   unsigned long long* stats;  // events, shadow steps, forwards, pool overflows, waves with rays
 };
@@ -278,8 +280,8 @@ __global__ __launch_bounds__(256) void path_init_kernel(PathG pg, CamG cam, int 
 }
 
 // n_in: device count of the input pool (written by the previous wave).  A resident
-// grid walks it in chunks of one wave's 64 records, so the loop bound is the same
-// for all lanes of a wave and the appends stay convergent.
+// grid takes its records through pg.cursor_in; the loop runs while any lane of the
+// wave holds a ray, so the refills and appends stay convergent.
 template <typename T, bool WIDE>
 __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, const float4* __restrict__ tf,
                                                          const PRay* __restrict__ in,
@@ -290,17 +292,38 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
   stage_tf(tf, sc.ntf, tfb, tfs, threadIdx.x, 256);
   __syncthreads();
   const int n_in = min(*n_in_dev, pg.out_cap);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && n_in > 0) atomicAdd(pg.stats + 4, 1ull);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (n_in > 0) atomicAdd(pg.stats + 4, 1ull);
+    *pg.cursor_out = 0;
+  }
   const int lane = threadIdx.x & 63;
-  const int wave0 = (blockIdx.x * 256 + threadIdx.x) & ~63;
-  const int stride = gridDim.x * 256;
+  const uint64_t lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
   unsigned ev = 0, st = 0, fw = 0;
-  for (int base = wave0; base < n_in; base += stride) {
-  const int i = base + lane;
+  // Each lane holds one ray.  Idle lanes take the next records of the input pool
+  // (one atomic per wave); a camera path stays in its lane across real collisions
+  // (its shadow ray goes to the next wave), so the wave's long chains overlap.
+  PRay r{};
+  bool have = false, exhausted = false;
+  for (;;) {
+    const uint64_t idle = __ballot(!have);
+    if (idle && !exhausted) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(pg.cursor_in, __popcll(idle));
+      base = __shfl(base, 0);
+      if (base + __popcll(idle) >= n_in) exhausted = true;
+      if (!have) {
+        const int i = base + __popcll(idle & lt_mask);
+        if (i < n_in) {
+          r = in[i];
+          have = true;
+        }
+      }
+    }
+    if (__ballot(have) == 0) break;
   PRay ra{}, rb{};
   bool ha = false, hb = false;
-  if (i < n_in) {
-    PRay r = in[i];
+  if (have) {
+    have = false;
     if (r.meta & kShadowRay) {
       const int slot = (int)((r.meta >> 16) & 0xff);
       for (int it = 0;; ++it) {
@@ -401,8 +424,7 @@ __global__ __launch_bounds__(256) void path_trace_kernel(SceneG sc, PathG pg, co
           r.w[0] = rr * cp;
           r.w[1] = rr * sp;
           r.w[2] = z;
-          ra = r;
-          ha = true;
+          have = true;  // the path goes on in this lane
           break;
         }
       }
@@ -567,6 +589,7 @@ void path_state_free(PathState* p) {
 template <typename T, bool WIDE>
 static void launch_trace(const SceneG& sc, const PathG& pg, const float4* tf, const PRay* in, const int* n,
                          int grid, size_t lds, hipStream_t st) {
+  // (pg.cursor_in counts the records of `in` taken; pg.cursor_out is cleared by the kernel)
   hipLaunchKernelGGL((path_trace_kernel<T, WIDE>), dim3((unsigned)grid), dim3(256), lds, st, sc, pg, tf, in, n);
 }
 
@@ -635,7 +658,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
     ps->brick_cap = K;
   }
   if (!ps->d_count) {
-    if ((s = dev_alloc((void**)&ps->d_count, 2 * sizeof(int), "path pool size")) != DPR_OK) return s;
+    if ((s = dev_alloc((void**)&ps->d_count, 4 * sizeof(int), "path pool sizes and cursors")) != DPR_OK) return s;
     if ((s = dev_alloc((void**)&ps->d_stats, 5 * sizeof(unsigned long long), "path stats")) != DPR_OK) return s;
     DPR_HIP(hipHostMalloc((void**)&ps->h_count, 2 * sizeof(int), hipHostMallocDefault));
   }
@@ -774,7 +797,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   pg.out_cap = (int)ps->cap;
   pg.stats = ps->d_stats;
   DPR_HIP(hipMemsetAsync(ps->contrib, 0, (size_t)slots * sizeof(float4), st));
-  DPR_HIP(hipMemsetAsync(ps->d_count, 0, 2 * sizeof(int), st));
+  DPR_HIP(hipMemsetAsync(ps->d_count, 0, 4 * sizeof(int), st));
   DPR_HIP(hipMemsetAsync(ps->d_stats, 0, 5 * sizeof(unsigned long long), st));
 
   int cur = 0;
@@ -803,8 +826,10 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
       const PRay* in = ps->pool[cur];
       const int* n_in = ps->d_count + cur;
       cur ^= 1;
+      pg.cursor_in = ps->d_count + 2 + (cur ^ 1);
       pg.out = ps->pool[cur];
       pg.out_count = ps->d_count + cur;
+      pg.cursor_out = ps->d_count + 2 + cur;
       DPR_HIP(hipMemsetAsync(pg.out_count, 0, sizeof(int), st));
       if (f16)
         wide ? launch_trace<__half, true>(sc, pg, w->tf_dev, in, n_in, grid, lds, st)
