@@ -97,6 +97,16 @@ __device__ __forceinline__ float2 load_pair_f32(const void* base, uint32_t boff)
   return make_float2(f.x, f.y);
 }
 
+// An FP16 brick's element: the halves of voxel x (low) and voxel x + 1 (high).
+__device__ __forceinline__ float2 unpack_pair_f16(uint32_t u) {
+  return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
+                     __half2float(__ushort_as_half((unsigned short)(u >> 16))));
+}
+__device__ __forceinline__ float2 load_pair_f16(const void* base, uint32_t boff) {
+  using GC = const char __attribute__((address_space(1)))*;
+  return unpack_pair_f16(*(const uint32_t __attribute__((address_space(1)))*)((GC)base + boff));
+}
+
 template <typename T> __device__ __forceinline__ float load_voxel(const T* p, uint32_t off);
 template <> __device__ __forceinline__ float load_voxel<float>(const float* p, uint32_t off) { return p[off]; }
 template <> __device__ __forceinline__ float load_voxel<__half>(const __half* p, uint32_t off) {

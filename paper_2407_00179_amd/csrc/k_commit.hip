@@ -54,7 +54,7 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(8
   while (j + 1 < jobs.n && bid >= jobs.job[j].blocks) bid -= jobs.job[j++].blocks;
   const CmJob& J = jobs.job[j];
   const E* __restrict__ src = (const E*)J.src;
-  E* __restrict__ dst = (E*)J.dst;
+  uint32_t* __restrict__ dst = (uint32_t*)J.dst;
   const int sx = J.sx, sy = J.sy;
   const int c = bid % J.chunks;
   const int my = (bid / J.chunks) % J.mdy, mz = bid / (J.chunks * J.mdy);
@@ -106,16 +106,22 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(8
             for (int k = 0; k < nrun; ++k) v[u][k] = s[k];
           }
           if (x_own && yp >= Y.cs && yp < Y.ce && zp >= Z.cs && zp < Z.ce) {
-            E* d = dst + ((size_t)blk_z(z, J.bsz) + blk_y(y, J.bsy) + blk_x(x0));
-            if (nrun == 4) {  // x0 is a multiple of 4: an aligned run of the block
-              V4 w;
-              w.x = v[u][0];
-              w.y = v[u][1];
-              w.z = v[u][2];
-              w.w = v[u][3];
-              *(V4*)d = w;
+            uint32_t* d = dst + ((size_t)blk_z(z, J.bsz) + blk_y(y, J.bsy) + blk_x(x0));
+            uint32_t w[4];
+            if constexpr (sizeof(E) == 2) {
+              // FP16: element x holds the halves of voxels x and x + 1 (the brick's
+              // last voxel has no x + 1; that half is never read)
+              const E after = x0 + 4 < sx ? s[4] : v[u][3];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) w[k] = (uint32_t)v[u][k] | ((uint32_t)(k < 3 ? v[u][k + 1] : after) << 16);
             } else {
-              for (int k = 0; k < nrun; ++k) d[k] = v[u][k];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) w[k] = v[u][k];
+            }
+            if (nrun == 4) {  // x0 is a multiple of 4: an aligned run of the block
+              *(uint4*)d = make_uint4(w[0], w[1], w[2], w[3]);
+            } else {
+              for (int k = 0; k < nrun; ++k) d[k] = w[k];
             }
           }
           live[u] = y >= Y.ws && y <= Y.we && z >= Z.ws && z <= Z.we;

@@ -133,7 +133,23 @@ __device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const 
   clamp_axis(p[0], sc.dims[0], b.slo[0], b.sdim[0], lx, g.fx);
   clamp_axis(p[1], sc.dims[1], b.slo[1], b.sdim[1], ly, g.fy);
   clamp_axis(p[2], sc.dims[2], b.slo[2], b.sdim[2], lz, g.fz);
-  if constexpr (WIDE) {
+  if constexpr (WIDE && sizeof(T) == 2) {
+    // FP16 elements hold voxel pairs (x, x + 1)
+    const uint32_t* pv = (const uint32_t*)b.data;
+    const uint32_t x0 = blk_x(lx);
+    const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
+    const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
+    const float2 c0 = unpack_pair_f16(pv[x0 + y0 + z0]), c1 = unpack_pair_f16(pv[x0 + y1 + z0]);
+    const float2 c2 = unpack_pair_f16(pv[x0 + y0 + z1]), c3 = unpack_pair_f16(pv[x0 + y1 + z1]);
+    g.v[0] = c0.x;
+    g.v[1] = c0.y;
+    g.v[2] = c1.x;
+    g.v[3] = c1.y;
+    g.v[4] = c2.x;
+    g.v[5] = c2.y;
+    g.v[6] = c3.x;
+    g.v[7] = c3.y;
+  } else if constexpr (WIDE) {
     const T* vox = (const T*)b.data;
     const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
     const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
@@ -147,7 +163,7 @@ __device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const 
     g.v[6] = load_voxel<T>(vox, x0 + y1 + z1);
     g.v[7] = load_voxel<T>(vox, x1 + y1 + z1);
   } else {
-    constexpr int SH = sizeof(T) == 2 ? 1 : 2;
+    constexpr int SH = 2;  // 4-byte elements: FP32 voxels or FP16 voxel pairs
     const uint32_t bsy = b.bsy << SH, bsz = b.bsz << SH;
     const uint32_t x0 = blkb_x<SH>(lx), x1 = blkb_x<SH>(lx + 1);
     const uint32_t y0 = blkb_y<SH>(ly, bsy), y1 = blkb_y<SH>(ly + 1, bsy);
@@ -176,15 +192,19 @@ __device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const 
         g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
       }
     } else {
-      const uint32_t a00 = x0 + y0, a10 = x1 + y0, a01 = x0 + y1, a11 = x1 + y1;
-      g.v[0] = load_voxel_b<T>(b.data, a00 + z0);
-      g.v[1] = load_voxel_b<T>(b.data, a10 + z0);
-      g.v[2] = load_voxel_b<T>(b.data, a01 + z0);
-      g.v[3] = load_voxel_b<T>(b.data, a11 + z0);
-      g.v[4] = load_voxel_b<T>(b.data, a00 + z1);
-      g.v[5] = load_voxel_b<T>(b.data, a10 + z1);
-      g.v[6] = load_voxel_b<T>(b.data, a01 + z1);
-      g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
+      // FP16: each element holds the voxel pair (x, x + 1), one aligned 4-byte load
+      (void)x1;
+      const uint32_t a00 = x0 + y0, a01 = x0 + y1;
+      const float2 c0 = load_pair_f16(b.data, a00 + z0), c1 = load_pair_f16(b.data, a01 + z0);
+      const float2 c2 = load_pair_f16(b.data, a00 + z1), c3 = load_pair_f16(b.data, a01 + z1);
+      g.v[0] = c0.x;
+      g.v[1] = c0.y;
+      g.v[2] = c1.x;
+      g.v[3] = c1.y;
+      g.v[4] = c2.x;
+      g.v[5] = c2.y;
+      g.v[6] = c3.x;
+      g.v[7] = c3.y;
     }
   }
 }

@@ -146,7 +146,7 @@ BrickG Brick::device_view(bool with_majorant, bool force_wide) const {
   g.bsy = (uint32_t)kBlockVoxels * (uint32_t)bdim[0];
   g.bsz = (uint32_t)kBlockVoxels * (uint32_t)bdim[0] * (uint32_t)bdim[1];
   g.majorant = with_majorant ? maj : nullptr;
-  g.wide = force_wide || (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * elem() > 0xffffffffull;
+  g.wide = force_wide || (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * 4u > 0xffffffffull;
   int sh = 0;
   while ((1 << sh) < mc) ++sh;
   g.mc_shift = sh;
@@ -513,7 +513,8 @@ dpr_status dpr_world_commit(dpr_world w) {
   const int mc = w->params.macrocell_cells;
   for (auto& b : w->bricks) {
     if (!b.blocked) {
-      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.elem() + kPairSlack;
+      // 4-byte elements: an FP32 voxel, or the FP16 voxel pair (x, x + 1)
+      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * 4u + kPairSlack;
       st = dev_alloc(&b.blocked, bytes, "blocked brick");
       if (st != DPR_OK) return st;
       // padding voxels (beyond the stored dims) are never written by the commit
