@@ -1,6 +1,6 @@
 """GPU parity at the full sizes of the large workloads, on sampled pixels: the
 27-brick FP16 volume rendered for 16 cameras by the batched renderer (the launch
-the bench times), and one rank's 2048x1536x1280 FP16 brick (an 8 GB blocked
+the bench times), and one rank's 2048x1536x1280 FP16 brick (a 16 GB blocked
 array, so voxel offsets take the 64-bit path)."""
 
 import numpy as np
@@ -75,7 +75,7 @@ def test_cfg3_batched_sampled(gpu_lib, dpr):
 
 def test_cfg5_brick_sampled(gpu_lib, dpr):
     """One rank's share of the 128-rank run: 2048x1536x1280 FP16 in one brick whose
-    blocked array is 8 GB (64-bit voxel offsets), rendered at 3840x2160."""
+    blocked array of voxel pairs is 16 GB (64-bit offsets), rendered at 3840x2160."""
     import torch
     cfg = get_config("cfg5")
     dims = cfg.dims
