@@ -54,9 +54,9 @@ OPS_PER_SAMPLE = 60
 #     from a plain 256 MiB device-to-device copy in the same runs);
 #   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
 MARCH_COUNTERS = {
-    "sources_sha256": "b93bb3e868a14a2aa1bd1cfe55b367d98ea7898dea895af1e7396031ba807e70",
-    "traffic_bytes_per_launch": 329274235,
-    "fetch_kib": 152068, "write_kib": 17458, "fetch_scale": 1.9997, "write_scale": 1.0,
+    "sources_sha256": "48f922c47420f72247d12cf51568fe708b51a44ee8530213a00e1298f964fbd2",
+    "traffic_bytes_per_launch": 324558168,
+    "fetch_kib": 149866, "write_kib": 17268, "fetch_scale": 1.9997, "write_scale": 1.0,
     "valu_lane_instr_per_sample": 68.8,
 }
 
