@@ -120,7 +120,10 @@ void dpr_world_release(dpr_world);
  * data are copied; the caller may free its buffer on return.  Every global dim
  * must be >= 2.  Ghost layers may not reach outside the global domain.
  * brick_id receives the brick's index (0, 1, ...), which is also its intrinsic
- * fragment id for compositing.  Adding a brick un-commits the world.            */
+ * fragment id for compositing.  Adding a brick un-commits the world.
+ * Device memory per brick: the linear copy (2 or 4 bytes per stored voxel) plus,
+ * after commit, the blocked copy at 4 bytes per voxel for either dtype (an F16
+ * element holds a voxel and its +x neighbour) and the macrocell arrays.         */
 dpr_status dpr_world_add_brick(dpr_world, const void* voxels, dpr_dtype dtype, int voxels_on_device,
                                const int64_t owned_lo[3], const int64_t owned_hi[3],
                                const int32_t ghost_lo[3], const int32_t ghost_hi[3], int32_t* brick_id);
