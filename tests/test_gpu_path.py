@@ -75,6 +75,25 @@ def test_paths_match_oracle(gpu_lib, dpr, dtype):
     assert np.ptp(want) > 0.05
 
 
+@pytest.mark.parametrize("bounces", [1, 12])
+def test_bounce_limits_match_oracle(gpu_lib, dpr, bounces):
+    """A path ends at its first real collision (1) or keeps scattering through many
+    (12, each one continuing in its lane within a wave), as in the oracle."""
+    dims = (28, 24, 20)
+    vol = _volume(dims, 61)
+    tf = _tf(3007, cut=0.1)
+    prm = RenderParams(0.5, 1.0, 30.0)
+    cam = orbit_camera(dims, 24, 20, dist=1.6)
+    pp = PathParams(max_bounces=bounces, spp=2, seed=9, **PP)
+    want, mg = oracle.render_path(vol, dims, tf, prm, pp, cam)
+    got, _, st = _gpu(dpr, gpu_lib, vol, dims, kd_split(dims, 5, seed=4, max_ratio=3.0), tf, prm, cam, bounces, 2, 9)
+    clear = mg > MARGIN
+    err = np.abs(got[:, :3] - want) / np.maximum(1.0, np.abs(want))
+    log(f"  {bounces} bounces: max rel err {err[clear].max():.2e}, {(~clear).sum()} near a flip; {st}")
+    assert err[clear].max() <= TOL and (~clear).sum() <= 0.05 * clear.size
+    assert st["events"] > 0
+
+
 def test_bricking_does_not_change_a_bit(gpu_lib, dpr):
     """The tentative collisions come from the path's own random numbers and the
     majorants of a grid over the whole volume, so any bricking gives the same
