@@ -18,7 +18,8 @@ What it computes, and where the paper fixes it:
   global domain, a 1D RGBA transfer function, per-brick ray/box clipping,
   early ray termination and depth = brick entry distance.  ``render.py``.
 * Macrocell value ranges and transfer-function majorants used by empty-space
-  skipping (decided in FP32, the kernel's precision).  ``macrocell.py``.
+  skipping, from their plain definitions (exact min/max; table coordinates in
+  FP64).  ``macrocell.py``.
 * Gradients of an L2 image loss with respect to the density grid and the
   transfer-function table.  ``grad.py``.
 * An independent loop-based brute-force renderer for tiny inputs.  ``brute.py``.
@@ -52,6 +53,8 @@ from .render import (  # noqa: F401
 from .composite import composite  # noqa: F401
 from .deep import FID_RANK, composite_deep, deep_frame  # noqa: F401
 from .path import PathParams, render_path, trace_paths  # noqa: F401
-from .iso import IsoParams, iso_classes, march_rays_iso, render_brick_iso, render_image_iso, trilinear_grad  # noqa: F401
-from .macrocell import macrocell_ranges, majorants, macrocell_grid  # noqa: F401
+from .iso import IsoParams, iso_class_ambiguous, iso_classes, march_rays_iso, render_brick_iso, render_image_iso, trilinear_grad  # noqa: F401
+from .macrocell import (  # noqa: F401
+    entry_decision_ambiguous, entry_range, macrocell_grid, macrocell_ranges, majorants, tf_coord,
+)
 from .grad import loss_and_grad, forward_image  # noqa: F401

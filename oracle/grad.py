@@ -28,7 +28,8 @@ from .render import RenderParams, camera_rays, clip_box
 
 
 def _corners(dims, g):
-    """Flat (z,y,x) indices (R,8) and weights (R,8) of the trilinear stencil (C2)."""
+    """Flat (z,y,x) indices (R,8), weights (R,8) and fractions (R,3) of the trilinear
+    stencil (C2); corner c = 4 dz + 2 dy + dx."""
     R = g.shape[0]
     i0 = np.empty((R, 3), dtype=np.int64)
     fr = np.empty((R, 3))
@@ -51,25 +52,22 @@ def _corners(dims, g):
                 idx[:, c] = ((i0[:, 2] + dz) * ny + (i0[:, 1] + dy)) * nx + (i0[:, 0] + dx)
                 wt[:, c] = wz * wy * wx
                 c += 1
-    return idx, wt
+    return idx, wt, fr
 
 
-def _lerp_value(vals, wt):
-    """Trilinear value from the 8 corner values (stencil order of _corners) in lerp
-    form a + f (b - a), exact on constant stencils; the fractions are recovered
-    from the weights (w1 = (1-fz)(1-fy) fx, ...)."""
-    fx = wt[:, 1] + wt[:, 3] + wt[:, 5] + wt[:, 7]
-    fy = wt[:, 2] + wt[:, 3] + wt[:, 6] + wt[:, 7]
-    fz = wt[:, 4] + wt[:, 5] + wt[:, 6] + wt[:, 7]
+def _lerp_value(vals, fr):
+    """Trilinear value from the 8 corner values (stencil order of _corners) and the
+    fractions fr = (fx, fy, fz), as nested lerps a + f (b - a): exact on constant
+    stencils, so a sample among voxels at a clamp bound sits exactly on it."""
 
     def lerp(a, b, f):
         return a + f * (b - a)
 
-    c00 = lerp(vals[:, 0], vals[:, 1], fx)
-    c01 = lerp(vals[:, 2], vals[:, 3], fx)
-    c10 = lerp(vals[:, 4], vals[:, 5], fx)
-    c11 = lerp(vals[:, 6], vals[:, 7], fx)
-    return lerp(lerp(c00, c01, fy), lerp(c10, c11, fy), fz)
+    c00 = lerp(vals[:, 0], vals[:, 1], fr[:, 0])
+    c01 = lerp(vals[:, 2], vals[:, 3], fr[:, 0])
+    c10 = lerp(vals[:, 4], vals[:, 5], fr[:, 0])
+    c11 = lerp(vals[:, 6], vals[:, 7], fr[:, 0])
+    return lerp(lerp(c00, c01, fr[:, 1]), lerp(c10, c11, fr[:, 1]), fr[:, 2])
 
 
 def _tf_parts(tf, v, lo, hi):
@@ -102,8 +100,8 @@ def _trace(vol_flat, dims, tf, params, o, d, record):
         s = s0[act] + k
         ell = np.maximum(np.minimum((s + 1.0) * dt, t_out[act]) - np.maximum(s * dt, t_in[act]), 0.0)
         p = o[act] + ((s + 0.5) * dt)[:, None] * d[act]
-        idx, wt = _corners(dims, p / h - 0.5)
-        v = _lerp_value(vol_flat[idx], wt)
+        idx, wt, fr = _corners(dims, p / h - 0.5)
+        v = _lerp_value(vol_flat[idx], fr)
         rgba, j, w, inside = _tf_parts(tf, v, params.tf_lo, params.tf_hi)
         tau = D * rgba[:, 3] * ell
         e = np.exp(-tau)

@@ -33,7 +33,7 @@ volume composites to the unsplit image (the split invariant holds).
 Skipping (an optimisation, must not change results; C21): a macrocell may be
 skipped only if its majorant is 0 and its value range lies on one side of v_iso
 by a margin m = 1e-6 max(|min|, |max|) (FP32 trilinear values stay within a few
-ulps of the range), all taken in FP32 as the kernel does.  ``iso_classes``
+ulps of the range), written here in FP64 from that definition.  ``iso_classes``
 encodes it per macrocell: the majorant where positive; else 0 (skippable, every
 sample below v_iso), -1 (skippable, every sample at or above v_iso) or 1 (must be
 sampled).
@@ -214,14 +214,28 @@ def render_image_iso(volume, dims, tf, params, iso, cam, px=None, py=None):
 
 
 def iso_classes(ranges, majorant, iso_value):
-    """Skip class per macrocell (C21) from (..., 2) ranges and majorants -> float32."""
-    lo = np.asarray(ranges[..., 0], dtype=np.float32)
-    hi = np.asarray(ranges[..., 1], dtype=np.float32)
+    """Skip class per macrocell (C21) from (..., 2) ranges and majorants -> float32,
+    from the plain definition in FP64: the majorant where positive; else 0 when
+    max < v_iso - m, -1 when min > v_iso + m, 1 otherwise, m = 1e-6 max(|min|, |max|)."""
+    lo = np.asarray(ranges[..., 0], dtype=np.float64)
+    hi = np.asarray(ranges[..., 1], dtype=np.float64)
     maj = np.asarray(majorant, dtype=np.float32)
-    v = np.float32(iso_value)
-    m = np.float32(1e-6) * np.maximum(np.abs(lo), np.abs(hi))
+    v = float(iso_value)
+    m = 1e-6 * np.maximum(np.abs(lo), np.abs(hi))
     below = hi < v - m
     above = lo > v + m
     out = np.where(maj > 0, maj, np.where(below, np.float32(0.0), np.where(above, np.float32(-1.0),
                                                                                 np.float32(1.0))))
     return out.astype(np.float32)
+
+
+def iso_class_ambiguous(ranges, iso_value, ulps=4):
+    """True where a range end lies within a few FP32 ulps of v_iso -+ m, so that the
+    class decided in FP32 may differ from the FP64 one (both are valid: the margin
+    m covers the FP32 rounding of trilinear values either way)."""
+    lo = np.asarray(ranges[..., 0], dtype=np.float64)
+    hi = np.asarray(ranges[..., 1], dtype=np.float64)
+    v = float(iso_value)
+    m = 1e-6 * np.maximum(np.abs(lo), np.abs(hi))
+    tol = ulps * float(np.spacing(np.float32(max(abs(v), 1e-30))))
+    return (np.abs(hi - (v - m)) <= tol) | (np.abs(lo - (v + m)) <= tol)

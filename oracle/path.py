@@ -75,11 +75,34 @@ def _draw(pid, e, kind, step, seed):
 BLOCK = 16
 
 
+def _entry_range32(ranges, n, lo, hi):
+    """The majorant's table-entry range [floor(x_min) - 1, ceil(x_max) + 1] with the
+    table coordinates taken in FP32: u = (v - lo) / (hi - lo), clamp to [0, 1],
+    x = u (N - 1).  Any entry range that covers the values gives an unbiased
+    estimator, but the tentative collisions, and so the paths, depend on sigma_bar
+    itself; the estimator is defined with this FP32 decision so that a path is one
+    definite sequence of events (an integer decided in the kernel's precision)."""
+    f32 = np.float32
+    out = []
+    for k in (0, 1):
+        v = np.asarray(ranges[..., k], dtype=f32)
+        u = (v - f32(lo)) / (f32(hi) - f32(lo))
+        out.append(np.minimum(np.maximum(u, f32(0.0)), f32(1.0)) * f32(n - 1))
+    e0 = np.maximum(np.floor(out[0]).astype(np.int64) - 1, 0)
+    e1 = np.minimum(np.ceil(out[1]).astype(np.int64) + 1, n - 1)
+    return e0, e1
+
+
 def block_majorants(volume, dims, tf, params: RenderParams):
-    """sigma_bar per 16^3-cell block of the global grid -> (Mz, My, Mx) FP64."""
-    from .macrocell import macrocell_ranges, majorants
+    """sigma_bar per 16^3-cell block of the global grid -> (Mz, My, Mx) FP64: D times
+    the largest TF opacity over the entry range of the block's value range (C13
+    windows, one voxel of apron)."""
+    from .macrocell import macrocell_ranges
     rng = macrocell_ranges(volume, (0, 0, 0), tuple(int(v) for v in dims), (0, 0, 0), BLOCK)
-    return params.density * majorants(rng, tf, params.tf_lo, params.tf_hi).astype(np.float64)
+    a = np.asarray(tf, dtype=np.float32)[:, 3]
+    e0, e1 = _entry_range32(rng, a.shape[0], params.tf_lo, params.tf_hi)
+    m = np.array([a[i:j + 1].max() for i, j in zip(e0.ravel(), e1.ravel())], dtype=np.float32)
+    return params.density * m.reshape(e0.shape).astype(np.float64)
 
 
 def _block_of(q, dims, h):

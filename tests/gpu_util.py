@@ -74,3 +74,77 @@ def check_bracketed(got_rgba, got_depth, got_n, oracle_at, ert, tol, what):
         assert np.all((got_n >= nlo) & (got_n <= nhi)), f"{what}: sample counts outside the oracle's"
     log(f"  {what}: max|gpu-oracle| = {err:.3e} (tol {tol:.0e}), bracketed pixels = {bracketed}")
     return err
+
+
+def tf_alpha_max(tf, ranges, lo=0.0, hi=1.0, chunk=1 << 15):
+    """FP64 largest table opacity over each value range [min, max] (..., 2): the
+    table is piecewise linear, so the maximum lies at an end or at a knot inside."""
+    tf = np.asarray(tf, dtype=np.float64)
+    n = tf.shape[0]
+    a = np.asarray(ranges[..., 0], dtype=np.float64).ravel()
+    b = np.asarray(ranges[..., 1], dtype=np.float64).ravel()
+    knots = lo + np.arange(n) * (hi - lo) / (n - 1)
+    out = np.empty(a.size)
+    for c0 in range(0, a.size, chunk):
+        aa, bb = a[c0:c0 + chunk], b[c0:c0 + chunk]
+        ends = np.maximum(oracle.tf_lookup(tf, aa, lo, hi)[:, 3], oracle.tf_lookup(tf, bb, lo, hi)[:, 3])
+        inside = (knots[None, :] > aa[:, None]) & (knots[None, :] < bb[:, None])
+        out[c0:c0 + chunk] = np.maximum(ends, np.max(np.where(inside, tf[None, :, 3], 0.0), axis=1))
+    return out.reshape(np.shape(ranges)[:-1])
+
+
+def _majorant_candidates(ranges, tf, lo, hi, eps=1e-4):
+    """Majorants of the entry ranges reachable by moving each end's table
+    coordinate by +-eps (the choices an FP32 decision can make)."""
+    a = np.asarray(tf, dtype=np.float32)[:, 3]
+    n = a.shape[0]
+    xs = []
+    for k in (0, 1):
+        v = np.asarray(ranges[..., k], dtype=np.float64).ravel()
+        xs.append((oracle.tf_coord(v, lo, hi, n), ((v > lo) & (v < hi)) * eps))
+    out = []
+    for s0 in (-1, 1):
+        for s1 in (-1, 1):
+            e0 = np.maximum(np.floor(xs[0][0] + s0 * xs[0][1]).astype(np.int64) - 1, 0)
+            e1 = np.minimum(np.ceil(xs[1][0] + s1 * xs[1][1]).astype(np.int64) + 1, n - 1)
+            out.append(np.array([a[i:j + 1].max() for i, j in zip(e0, e1)], dtype=np.float32))
+    return np.stack(out, axis=1)
+
+
+def check_majorants(got, ranges, tf, what, lo=0.0, hi=1.0):
+    """GPU majorants against the FP64 definition: equal wherever a range end's entry
+    decision is not within FP32 rounding of an entry boundary; there, one of the
+    neighbouring choices.  Everywhere: no less than the largest opacity over the
+    range, and 0 only where the table is transparent over the whole range."""
+    want = oracle.majorants(ranges, tf, lo, hi)
+    amb = oracle.entry_decision_ambiguous(ranges, np.shape(tf)[0], lo, hi)
+    assert np.array_equal(got[~amb], want[~amb]), f"{what}: {np.count_nonzero(got[~amb] != want[~amb])} majorants differ"
+    if amb.any():
+        cand = _majorant_candidates(ranges[amb], tf, lo, hi)
+        assert np.all(np.any(cand == got[amb][:, None], axis=1)), f"{what}: ambiguous majorant not a valid choice"
+    amax = tf_alpha_max(tf, ranges, lo, hi)
+    # (the FP64 lerp between two equal entries may exceed them by an ulp)
+    assert np.all(got.astype(np.float64) >= amax * (1 - 1e-12)), f"{what}: a majorant below the range's opacity"
+    assert np.all(amax[got == 0.0] == 0.0), f"{what}: a zero majorant over an opaque range"
+    return int(np.count_nonzero(amb))
+
+
+def check_iso_classes(got, ranges, tf, v_iso, what, lo=0.0, hi=1.0):
+    """Majorants with iso-surface skip classes: positive entries are majorants
+    (check_majorants); a zero majorant becomes 0 (range strictly below v_iso), -1
+    (strictly above) or 1 (sample it), equal to the FP64 definition except where a
+    range end lies within FP32 rounding of a decision boundary."""
+    want_m = oracle.majorants(ranges, tf, lo, hi)
+    want = oracle.iso_classes(ranges, want_m, v_iso)
+    amb = oracle.entry_decision_ambiguous(ranges, np.shape(tf)[0], lo, hi) | oracle.iso_class_ambiguous(ranges, v_iso)
+    assert np.array_equal(got[~amb], want[~amb]), f"{what}: {np.count_nonzero(got[~amb] != want[~amb])} classes differ"
+    pos = got > 0
+    amax = tf_alpha_max(tf, ranges, lo, hi)
+    assert np.all(got[pos].astype(np.float64) >= amax[pos] * (1 - 1e-12)), f"{what}: a majorant below the range's opacity"
+    cls = ~pos
+    assert np.all(amax[cls] == 0.0), f"{what}: a skip class over an opaque range"
+    r64 = ranges.astype(np.float64)
+    assert np.all(r64[got == 0.0][:, 1] < v_iso), f"{what}: class 0 with a value at or above v_iso"
+    assert np.all(r64[got == -1.0][:, 0] > v_iso), f"{what}: class -1 with a value below v_iso"
+    assert np.all(np.isin(got[cls], np.array([0.0, -1.0, 1.0], dtype=np.float32))), f"{what}: unknown class"
+    return int(np.count_nonzero(amb))

@@ -7,7 +7,8 @@ import oracle
 from oracle import RenderParams
 from synth import (Camera, even_split, extract_brick, get_config, kd_split, make_blobs, make_tf, make_volume_small,
                    orbit_camera, pixel_subset)
-from tests.gpu_util import TOL_F16, TOL_F32, check_bracketed, frame_np, log, make_world, oracle_brick
+from tests.gpu_util import (TOL_F16, TOL_F32, check_bracketed, check_majorants, frame_np, log, make_world,
+                            oracle_brick)
 
 pytestmark = pytest.mark.gpu
 
@@ -148,10 +149,10 @@ def test_macrocells_and_majorants_bitwise(gpu_lib, dpr):
         for i, (lo, hi) in enumerate(boxes):
             b = extract_brick(vol, dims, lo, hi)
             want_r = oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, mc)
-            want_m = oracle.majorants(want_r, tf)
             got_r, got_m = w.macrocells(i)
             assert np.array_equal(got_r, want_r), (mc, i)
-            assert np.array_equal(got_m, want_m), (mc, i)
+            amb = check_majorants(got_m, want_r, tf, f"mc {mc} brick {i}")
+            log(f"  mc {mc} brick {i}: {got_m.size} majorants, {amb} with an FP32-ambiguous entry range")
             assert np.any(got_m == 0.0) or mc == 16
         w.release()
 
@@ -219,7 +220,7 @@ def test_ghost_width_does_not_change_a_bit(gpu_lib, dpr, dtype):
             b = extract_brick(vol, dims, lo, hi, ghost)
             want = oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, 8)
             assert np.array_equal(ranges[i][0], want), (ghost, i)
-            assert np.array_equal(ranges[i][1], oracle.majorants(want, tf)), (ghost, i)
+            check_majorants(ranges[i][1], want, tf, f"ghost {ghost} brick {i}")
 
 
 @pytest.mark.parametrize("dims,dtype", [((150, 9, 7), np.float32), ((300, 8, 6), np.float16),
@@ -239,7 +240,7 @@ def test_macrocells_wide_bricks(gpu_lib, dpr, dims, dtype):
                 want_r = oracle.macrocell_ranges(b.data, lo, hi, b.ghost_lo, mc)
                 got_r, got_m = w.macrocells(i)
                 assert np.array_equal(got_r, want_r), (dims, len(boxes), mc, i)
-                assert np.array_equal(got_m, oracle.majorants(want_r, tf)), (dims, len(boxes), mc, i)
+                check_majorants(got_m, want_r, tf, f"{dims} {len(boxes)} bricks mc {mc} brick {i}")
             w.release()
 
 

@@ -66,6 +66,65 @@ def test_majorant_zero_means_exactly_transparent():
     assert oracle.majorants(np.array([[2.0, 3.0]], dtype=np.float32), tf)[0] == tf[n - 2:, 3].max()
 
 
+def _tf_alpha_max(tf, a, b, lo=0.0, hi=1.0):
+    """Largest opacity of the piecewise-linear table over values [a, b], by evaluating
+    it at both ends and at every table knot between them (the maximum of a
+    piecewise-linear function lies at one of those)."""
+    n = tf.shape[0]
+    knots = lo + np.arange(n) * (hi - lo) / (n - 1)
+    vs = np.concatenate([[a, b], knots[(knots > a) & (knots < b)]])
+    return float(oracle.tf_lookup(tf, vs, lo, hi)[:, 3].max())
+
+
+def test_majorant_entry_window_is_one_entry_wide_each_side():
+    """The majorant is the largest opacity over the range widened by one table entry
+    on each side, neither less nor more: a zero majorant means the table is
+    transparent within one entry width of the range, and a positive one means it is
+    not transparent within two entry widths."""
+    n = 256
+    tf = np.zeros((n, 4), dtype=np.float32)
+    tf[:, :3] = 0.5
+    tf[200:, 3] = np.linspace(0.1, 1.0, n - 200)        # opaque from entry 200 on
+    de = 1.0 / (n - 1)
+    rng = np.random.default_rng(7)
+    # ranges ending at random fractional table coordinates below and around entry 200
+    ends = (rng.random(2000) * 8.0 + 194.0) * de
+    ranges = np.stack([ends - 5 * de, ends], axis=1).astype(np.float32)
+    maj = oracle.majorants(ranges, tf)
+    for (a, b), mj in zip(ranges.astype(np.float64), maj):
+        if mj == 0.0:
+            assert _tf_alpha_max(tf, a - de, b + de) == 0.0, (a, b)
+        else:
+            assert _tf_alpha_max(tf, a - 2 * de, b + 2 * de) > 0.0, (a, b)
+        assert mj >= _tf_alpha_max(tf, a, b)
+    assert np.any(maj == 0.0) and np.any(maj > 0.0)
+    # an end exactly on entry 198 (x_max = 198): entries up to 199 are transparent
+    r = np.array([[0.1, 198 * de]], dtype=np.float32)
+    assert float(r[0, 1]) * (n - 1) != 198.0 or oracle.majorants(r, tf)[0] == 0.0
+
+
+def test_majorant_is_the_fp64_definition():
+    """Entry ranges follow the FP64 table coordinate: x_max just above an integer k
+    (by 2^-40 of an entry, far below FP32 resolution) reaches entry k + 2.  A
+    257-entry table on [0, 1] makes x = 256 v exact."""
+    n = 257
+    tf = np.zeros((n, 4), dtype=np.float32)
+    tf[102, 3] = 0.5
+    k = 100.0 / 256.0
+    e0, e1 = oracle.entry_range(np.array([[0.0, k]]), n)
+    assert e1[0] == 101
+    above = np.array([[0.0, k + 2.0 ** -48]])
+    e0, e1 = oracle.entry_range(above, n)
+    assert e1[0] == 102
+    assert oracle.entry_decision_ambiguous(above, n)[0]
+    assert not oracle.entry_decision_ambiguous(np.array([[0.0, 100.4 / 256.0]]), n)[0]
+    assert oracle.majorants(np.array([[0.0, 100.4 / 256.0]]), tf)[0] == 0.5
+    assert oracle.majorants(np.array([[0.0, 99.4 / 256.0]]), tf)[0] == 0.0
+    # the lower end: x_min = 104 reaches entry 103, x_min just below 104 reaches 102
+    assert oracle.entry_range(np.array([[104.0 / 256.0, 0.5]]), n)[0][0] == 103
+    assert oracle.entry_range(np.array([[104.0 / 256.0 - 2.0 ** -48, 0.5]]), n)[0][0] == 102
+
+
 # ----------------------------------------------------------------- gradients (P-c9)
 def _tiny_problem(seed=0):
     dims = (6, 5, 7)
@@ -119,15 +178,18 @@ def test_gradient_matches_central_differences():
         assert abs(fd - gT.ravel()[f]) <= 1e-6 * max(abs(fd), 1e-6), (f, fd, gT.ravel()[f])
 
 
-def _torch_render(vol_t, tf_t, dims, prm, cam):
-    """The same quadrature re-expressed with torch FP64 ops, for torch.autograd."""
+def _torch_render(vol_t, tf_t, dims, prm, cam, plateau=None):
+    """The same quadrature re-expressed with torch FP64 ops, for torch.autograd.  The
+    trilinear value is taken as nested lerps a + f (b - a), so a sample whose eight
+    corners all hold a clamp bound (0 or 1) sits exactly on it; ``plateau`` (a list)
+    collects those sample values."""
     h = 1.0 / max(dims)
     dt = prm.step_voxels * h
     n = tf_t.shape[0]
     py, px = np.mgrid[0:cam.height, 0:cam.width]
     o, d = oracle.camera_rays(cam, px.ravel(), py.ravel())
     t0, t1, hit = oracle.clip_box(o, d, np.zeros(3), np.array(dims) * h)
-    flat = vol_t.reshape(-1)
+    vol3 = vol_t.reshape(dims[2], dims[1], dims[0])
     out = []
     for r in range(o.shape[0]):
         if not hit[r]:
@@ -142,13 +204,12 @@ def _torch_render(vol_t, tf_t, dims, prm, cam):
             g = [min(max(p[a] / h - 0.5, 0.0), dims[a] - 1.0) for a in range(3)]
             i0 = [min(int(math.floor(g[a])), dims[a] - 2) for a in range(3)]
             f = [g[a] - i0[a] for a in range(3)]
-            v = 0.0
-            for dz in (0, 1):
-                for dy in (0, 1):
-                    for dx in (0, 1):
-                        w = (f[0] if dx else 1 - f[0]) * (f[1] if dy else 1 - f[1]) * (f[2] if dz else 1 - f[2])
-                        idx = ((i0[2] + dz) * dims[1] + i0[1] + dy) * dims[0] + i0[0] + dx
-                        v = v + w * flat[idx]
+            cell = vol3[i0[2]:i0[2] + 2, i0[1]:i0[1] + 2, i0[0]:i0[0] + 2]
+            ex = cell[:, :, 0] + f[0] * (cell[:, :, 1] - cell[:, :, 0])
+            ey = ex[:, 0] + f[1] * (ex[:, 1] - ex[:, 0])
+            v = ey[0] + f[2] * (ey[1] - ey[0])
+            if plateau is not None and float(v) in (0.0, 1.0):
+                plateau.append(float(v))
             u = torch.clamp((v - prm.tf_lo) / (prm.tf_hi - prm.tf_lo), 0.0, 1.0)
             x = u * (n - 1)
             j = min(int(math.floor(float(x))), n - 2)
@@ -173,6 +234,36 @@ def test_gradient_matches_torch_autograd_fp64():
     assert abs(Lt.item() - L) < 1e-13
     assert np.allclose(vt.grad.numpy(), gV, atol=1e-12, rtol=1e-9)
     assert np.allclose(tt.grad.numpy(), gT, atol=1e-12, rtol=1e-9)
+
+
+def test_gradient_on_clamp_plateaus_matches_torch_autograd_fp64():
+    """Samples exactly on the clamped plateaus v = 0 and v = 1 (u = 0 or 1).  The
+    oracle counts 0 <= u <= 1 as inside the table, so the value gradient there is
+    the slope of the end segment of the table, as with torch.clamp, whose gradient
+    passes at the bounds; counting them as outside would give 0 there."""
+    dims = (7, 6, 5)
+    base = random_volume(dims, 92).astype(np.float64)
+    vol = np.clip(2.2 * base - 0.35, 0.0, 1.0)          # wide regions of exact 0 and exact 1
+    assert np.count_nonzero(vol == 0.0) > 20 and np.count_nonzero(vol == 1.0) > 20
+    rng = np.random.default_rng(91)
+    tf = rng.random((256, 4))                            # every segment sloped, both ends included
+    tf[:, 3] = 0.1 + 0.8 * tf[:, 3]
+    cams = [orbit_camera(dims, 6, 5), Camera((-1.0, 1.9, 1.1), (0.5, 0.42, 0.36), (0.0, 0.0, 1.0), 45.0, 5, 6)]
+    prm = RenderParams(step_voxels=0.5, ert=1.0, density=6.0)
+    tgt = [np.random.default_rng(92).random((c.height, c.width, 4)) * 0.5 for c in cams]
+    L, gV, gT = _loss_grad(vol, dims, tf, prm, cams, tgt)
+    vt = torch.tensor(vol, dtype=torch.float64, requires_grad=True)
+    tt = torch.tensor(tf, dtype=torch.float64, requires_grad=True)
+    n_el = sum(t.size for t in tgt)
+    on = []
+    Lt = sum(((_torch_render(vt, tt, dims, prm, c, on) - torch.tensor(t)) ** 2).sum() for c, t in zip(cams, tgt)) / n_el
+    assert on.count(0.0) >= 10 and on.count(1.0) >= 10, (on.count(0.0), on.count(1.0))
+    Lt.backward()
+    assert abs(Lt.item() - L) < 1e-13
+    assert np.allclose(vt.grad.numpy(), gV, atol=1e-13, rtol=1e-9)
+    assert np.allclose(tt.grad.numpy(), gT, atol=1e-13, rtol=1e-9)
+    # the plateau voxels carry gradient (the end segments' slopes are not zero)
+    assert np.abs(gV[vol == 1.0]).max() > 1e-4 and np.abs(gV[vol == 0.0]).max() > 1e-4
 
 
 def test_gradient_constant_volume_closed_form():
