@@ -224,6 +224,23 @@ dpr_status dpr_render_partial(dpr_world, int32_t brick_id, dpr_frame out);
 dpr_status dpr_composite(dpr_device, const dpr_frame* parts, const int32_t* frag_ids, int32_t k,
                          dpr_frame out);
 
+/* dpr_composite for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation after set-up.
+ * Same arguments, same kernels and the same bits as dpr_composite, but every
+ * piece of device scratch (fragment table, depth prior, fix-up counters and
+ * pixel list) lives in one fixed array of the library, about 33 MB per GPU, held
+ * from the first dpr_device_create on that GPU until the process ends.  The call
+ * allocates nothing (no hipMalloc/hipFree, no pinned or pageable staging, no
+ * host heap on success) and copies nothing from the host: the fragment table
+ * travels in kernel arguments.  Limit: out->w * out->h <= 8388608 pixels
+ * (3840 x 2160 fits); larger frames return DPR_ERR_UNSUPPORTED.  Every call on
+ * one GPU shares that GPU's array: calls enqueued on the same stream are
+ * ordered, calls that overlap on different streams of one GPU race (the caller
+ * serialises them).  The array keeps the last call's contents; the counters that
+ * must start at zero are cleared on the device stream by every call.           */
+dpr_status dpr_composite_noalloc(dpr_device, const dpr_frame* parts, const int32_t* frag_ids, int32_t k,
+                                 dpr_frame out);
+
 /* The collective render of section 3.2 on one GPU: render every brick of the
  * world to fragments and composite them into `out`.  By default the bricks go
  * through the persistent batched renderer below (one camera); with

@@ -314,6 +314,15 @@ def composite(dev: Device, parts, out: Frame, ids=None):
     check(lib.dpr_composite(dev.h, fr, idarr, k, out.h))
 
 
+def composite_noalloc(dev: Device, parts, out: Frame, ids=None):
+    """``composite`` through the entry point that allocates nothing (its scratch is
+    the library's fixed per-GPU array; frames up to 8,388,608 pixels)."""
+    k = len(parts)
+    fr = (C.c_void_p * k)(*[f.h.value for f in parts])
+    idarr = None if ids is None else (C.c_int32 * k)(*[int(i) for i in ids])
+    check(lib.dpr_composite_noalloc(dev.h, fr, idarr, k, out.h))
+
+
 # ---------------------------------------------------------------- differentiable render
 def _cam_array(cams):
     return (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])

@@ -90,6 +90,7 @@ _SIGS = {
     "dpr_frame_release": ([P], None),
     "dpr_render_partial": ([P, C.c_int32, P], C.c_int),
     "dpr_composite": ([P, P, P, C.c_int32, P], C.c_int),
+    "dpr_composite_noalloc": ([P, P, P, C.c_int32, P], C.c_int),
     "dpr_render_frame": ([P, P], C.c_int),
     "dpr_render_batch": ([P, P, C.c_int32, P, C.c_uint32], C.c_int),
     "dpr_autotune_batch": ([P, P, C.c_int32, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdpr.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["runtime.hip", "k_render.hip", "k_commit.hip", "k_composite.hip", "k_batch.hip", "k_train.hip", "k_path.hip"]
+SOURCES = ["runtime.hip", "k_render.hip", "k_commit.hip", "k_composite.hip", "k_batch.hip", "k_train.hip", "k_path.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -318,6 +318,11 @@ dpr_status dpr_device_create(int hip_device, void* hip_stream, dpr_device* out) 
   d->stream = (hipStream_t)hip_stream;
   d->cu_count = prop.multiProcessorCount;
   d->wave_size = prop.warpSize;
+  const dpr_status st = noalloc_setup(d);
+  if (st != DPR_OK) {
+    delete d;
+    return st;
+  }
   *out = d;
   return DPR_OK;
 }

@@ -57,6 +57,9 @@ struct dpr_device_t {
   int* fix_list = nullptr;
   size_t fix_cap = 0;
   float* comp_prior = nullptr;  // sampled nearest depth per source (kCompPriorFloats)
+  // device address of the library's fixed scratch array on this GPU
+  // (dpr_composite_noalloc), looked up when the handle is created
+  void* noalloc_scratch = nullptr;
 };
 
 struct dpr_frame_t {
@@ -144,6 +147,11 @@ dpr_status check_camera(const dpr_camera* c);
 dpr_status ensure_majorants(dpr_world_t* w);
 dpr_status render_frame_batched(dpr_world w, dpr_frame out);
 dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out);
+// Largest frame (pixels) dpr_composite_noalloc takes: its fix-up list is sized
+// for it (3840 x 2160 fits).
+constexpr size_t kNoAllocMaxPixels = (size_t)1 << 23;
+// Look up this GPU's copy of the fixed scratch array (the device is current).
+dpr_status noalloc_setup(dpr_device d);
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
                       const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts = nullptr);
 
