@@ -1,33 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark of the data-parallel brick renderer + sort-last compositor on one MI355X.
 
-Default workload (one "step" = the whole hot path once): a 512^3 FP32 blob+noise
-volume split into 2x2x2 bricks of 256^3 owned cells with one ghost layer
-(257^3 stored), rendered at 1024x1024 through one camera:
-  commit (8^3-blocked copy of every brick + macrocell min/max ranges, one pass)
+Headline workload (one "step" = the whole hot path once) -- one rank's share of
+a 128-rank large-volume run: a 2048x1536x1280 FP16 blob + fBm brick (8.05 GB)
+rendered at 3840x2160 through one camera, step 0.5 voxel, ERT 0.99, 16^3
+macrocells, then composited with 127 synthetic RGBA32F+depth frames of the
+other ranks (depth slabs in front of and behind the brick):
+  commit (8^3-blocked copy + macrocell min/max ranges, one pass)
   -> transfer-function majorants
-  -> 8 per-brick emission-absorption ray marches (partial RGBA+depth frames)
-  -> sort-last composite of the 8 partial frames.
-value = logical samples per second (lattice segments of positive length
-processed before termination, skipped ones included), in Msamples/s.
+  -> batched persistent march of the brick (+ its tile composite)
+  -> sort-last composite of the K = 128 frames.
+value = logical samples per second of the step (lattice segments of positive
+length processed before termination, skipped ones included), in Msamples/s.
 
-Extra sections (same JSON line): the K=128 compositor at 3840x2160, the batched
-persistent renderer against plain per-brick launches on the 27-brick 16-camera
-workload, the backward/forward time ratio of the differentiable renderer, deep
-(multi-fragment) frames of an interleaved 8-rank partition, the opaque
-iso-surface mixed with the volume, and data-parallel path tracing with rays
-forwarded between bricks.
+Reported beside it, from the same run: per-phase HIP-event times, the commit's
+and the K=128 composite's GB/s against the 8 TB/s HBM peak, the plain per-brick
+march, the VALU ceiling and the measured gather ceiling of the march, the
+measured copy ceiling, and the counters of the dominant kernel from the
+committed rocprofv3 summary when its sources are unchanged.  Secondary keys: the
+512^3 FP32 2x2x2 step, the batched renderer on the 27-brick 16-camera FP16
+workload, the backward/forward ratio of the differentiable renderer, deep
+frames, iso-surfaces and path tracing.
 
-The CPU baseline (the FP64 oracle, not tuned) runs first, before any GPU use,
-on a bounded pixel sample of the default workload, over a fork pool of host cores.
+The CPU baseline (the FP64 oracle, not tuned) runs last, over a spawned pool of
+host processes reading the same input bytes from shared memory: the render on a
+pixel sample of the headline brick, the K=128 composite on a band of rows, and
+the gradient on a pixel sample of one 512x512 camera of the 256^3 training
+workload.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import multiprocessing as mp
 import os
+import re
+import shutil
 import sys
 import time
 
@@ -45,79 +55,185 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # CUs x lanes x clock: lane-op slots 
 # the trilinear lerps, TF lookup + lerp, one exp, the accumulate FMAs, the advance
 # and the termination compares.
 OPS_PER_SAMPLE = 60
-
-# Counters of one batch_march_kernel launch on the default workload, valid only for
-# the kernel sources they were taken on (SHA-256 over march.h, k_batch.hip and
-# device_common.h, in that order); after any change the bench reports null for them
-# until they are measured again:
-#   traffic: HBM bytes per launch, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB; factors
-#     from a plain 256 MiB device-to-device copy in the same runs);
-#   valu_lane_instr_per_sample: SQ_INSTS_VALU x 64 / logical samples.
-MARCH_COUNTERS = {
-    "sources_sha256": "48f922c47420f72247d12cf51568fe708b51a44ee8530213a00e1298f964fbd2",
-    "traffic_bytes_per_launch": 324558168,
-    "fetch_kib": 149866, "write_kib": 17268, "fetch_scale": 1.9997, "write_scale": 1.0,
-    "valu_lane_instr_per_sample": 68.8,
+CSRC = os.path.join(ROOT, "paper_2407_00179_amd", "csrc")
+# source files whose change invalidates a kernel's stored counters
+KERNEL_SOURCES = {
+    "batch_march_kernel": ("march.h", "k_batch.hip", "device_common.h"),
+    "commit_kernel": ("k_commit.hip", "commit_span.h", "device_common.h", "kernels.h"),
+    "composite_fast_kernel": ("k_composite.hip", "composite.h", "kernels.h"),
 }
 
 
-def march_sources_sha256():
-    import hashlib
+def sources_sha256(kernel):
     h = hashlib.sha256()
-    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2407_00179_amd", "csrc")
-    for f in ("march.h", "k_batch.hip", "device_common.h"):
-        with open(os.path.join(base, f), "rb") as fh:
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def stored_counters(kernel, workload):
+    """Counters of `kernel` on `workload` from the committed rocprofv3 summaries
+    (a `counters-json:` line in a profiles/*.md file), if taken on the current
+    sources; else None."""
+    pdir = os.path.join(ROOT, "profiles")
+    want = sources_sha256(kernel)
+    for name in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                m = re.match(r"\s*counters-json:\s*(\{.*\})\s*$", line)
+                if not m:
+                    continue
+                c = json.loads(m.group(1))
+                if c.get("kernel") == kernel and c.get("workload") == workload and c.get("sources_sha256") == want:
+                    c["file"] = "profiles/" + name
+                    return c
+    return None
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# ---------------------------------------------------------------- CPU baseline (oracle)
-_CPU = {}
-
-
-def _cpu_worker(args):
-    import oracle
-    bricks, vol_dims, tf, prm, cam, px, py = _CPU["data"]
-    parts = []
-    samples = 0
-    for b in bricks:
-        r, z, n = oracle.render_brick(b.data, b.stored_lo, vol_dims, b.lo, b.hi, tf, prm, cam, px[args], py[args])
-        parts.append((r, z))
-        samples += int(n.sum())
-    oracle.composite(np.stack([p[0] for p in parts]), np.stack([p[1] for p in parts]))
-    return samples
-
-
-def cpu_baseline(bricks, dims, tf, prm, cam, stride, cores):
-    import oracle  # noqa: F401  (imported before forking)
-    py, px = np.mgrid[0:cam.height:stride, 0:cam.width:stride]
-    px, py = px.ravel(), py.ravel()
-    _CPU["data"] = (bricks, dims, tf, prm, cam, px, py)
-    chunks = np.array_split(np.arange(px.size), cores * 4)
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        samples = sum(pool.map(_cpu_worker, chunks))
-    dt = time.perf_counter() - t0
-    return dict(value=samples / dt / 1e6, unit="Msamples/s", cores=cores, kind="oracle",
-                sample=f"every {stride}th pixel in x and y ({px.size} rays) x {len(bricks)} bricks + composite, "
-                       f"{samples} logical samples in {dt:.1f} s, FP64 numpy over a fork pool")
-
-
-# ---------------------------------------------------------------- GPU sections
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
-    dev = dpr.Device(0)
+# ---------------------------------------------------------------- headline: one rank's share, K = 128
+def brick_depth_range(dims, cam):
+    """Nearest point and farthest corner of the brick's box from the eye."""
+    h = 1.0 / max(dims)
+    hi = np.array(dims, dtype=np.float64) * h
+    eye = np.array(cam.eye, dtype=np.float64)
+    t_min = float(np.linalg.norm(eye - np.clip(eye, 0.0, hi)))
+    t_max = float(max(np.linalg.norm(eye - np.array([x, y, z])) for x in (0.0, hi[0]) for y in (0.0, hi[1])
+                      for z in (0.0, hi[2])))
+    return t_min, t_max
+
+
+def bench_rank_share(args, dpr, torch, dev, keep_host):
+    from synth import make_volume_large, synthetic_frames
+    cfg = get_config("cfg5")
+    dims = cfg.dims
+    (W, H), K = cfg.image, 128
+    cam = orbit_camera(dims, W, H)
+    log("  generating the 2048x1536x1280 FP16 brick on the GPU")
+    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range, log_uniform=cfg.log_sigma)
+    vol = make_volume_large(dims, blobs, cfg.seeds["volume"], cfg.noise_amp, cfg.fbm_periods,
+                            device=dev.torch_device)
+    host = vol.cpu().numpy() if keep_host else None
+    tf = make_tf(cfg.seeds["tf"])
     w = dpr.World(dev, dims)
-    # batched render enqueued directly (no graph replay) so HIP events bracket each kernel
-    prm = dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH)
-    w.set_params(prm)
+    # batched render enqueued directly (no graph replay) so HIP events bracket its kernels
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH))
+    w.add_brick(vol, (0, 0, 0), dims, (0, 0, 0), (0, 0, 0))
+    voxel_bytes = vol.numel() * vol.element_size()
+    del vol
+    torch.cuda.empty_cache()
+    w.commit()
+    w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+    w.set_camera(cam)
+    # logical samples (counted by the plain march) and the plain per-brick march itself
+    cf = dpr.Frame(dev, W, H, counts=True)
+    w.render_partial(0, cf)
+    dev.sync()
+    samples = int(cf.counts.sum().item())
+    hits = int(torch.isfinite(cf.depth).sum().item())
+    ms_plain = _timed(torch, lambda: w.render_partial(0, cf), 3)
+    # gather ceiling: the march's loads for the same samples, no dependence between samples
+    sink = torch.empty((H, W), dtype=torch.float32, device=dev.torch_device)
+    w.measure_gather(0, cf.counts, sink)
+    ms_gather = _timed(torch, lambda: w.measure_gather(0, cf.counts, sink), 5)
+    # the K = 128 frames: frame 0 is this rank's, rendered every step; 127 synthetic
+    t_min, t_max = brick_depth_range(dims, cam)
+    rgba = torch.empty((K, H, W, 4), dtype=torch.float32, device=dev.torch_device)
+    depth = torch.empty((K, H, W), dtype=torch.float32, device=dev.torch_device)
+    synthetic_frames(K - 1, W, H, t_min, t_max, cfg.seeds["frames"], dev.torch_device, rgba[1:], depth[1:])
+    frames = [dpr.Frame(dev, W, H, rgba=rgba[k], depth=depth[k]) for k in range(K)]
+    real = frames[0]
+    out = dpr.Frame(dev, W, H)
+    ids = [int(i) for i in np.random.default_rng(cfg.seeds["frames"]).permutation(K)]
+    tile = (8, 8)
+    w.set_batch_tile(*tile)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        w.commit()                                            # blocked copy + macrocell ranges
+        if ev is not None:
+            ev[1].record()
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)   # majorants follow (at the render)
+        w.render_frame(real)                                  # majorants, batched march, tile composite
+        if ev is not None:
+            ev[2].record()
+        dpr.composite(dev, frames, out, ids=ids)              # K = 128 sort-last composite
+        if ev is not None:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    march_ms, tile_ms = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+        a, c = w.batch_timings()    # HIP events recorded around the march and tile kernels on the device stream
+        march_ms.append(a)
+        tile_ms.append(c)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    commit_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    render_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    comp_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    # the rendered frame equals the plain per-brick march bit for bit
+    same = bool(torch.equal(real.rgba, cf.rgba) and torch.equal(real.depth, cf.depth))
+    live = int(torch.isfinite(depth).sum().item())
+    comp_alg = K * W * H * 4 + live * 16 + W * H * 20
+    ncells = int(np.prod([(d + cfg.macrocell - 1) // cfg.macrocell for d in dims]))
+    commit_alg = 2 * voxel_bytes + 8 * ncells          # every stored voxel read once and written once
+    # FP16 bricks whose voxel-pair copy would reach 4 GiB (this one) are stored as
+    # 2-byte voxels, so the commit writes exactly the algorithmic bytes
+    commit_actual = commit_alg
+    res = dict(ms_per_step=wall * 1e3 / args.steps, samples=samples, hit_pixels=hits, tile=tile,
+               phases=dict(commit=commit_ms, render_frame=render_ms, batch_march=float(np.mean(march_ms)),
+                           tile_composite=float(np.mean(tile_ms)), composite_k128=comp_ms),
+               ms_plain_march=ms_plain, ms_gather_probe=ms_gather, identical_to_plain=same,
+               comp_alg=comp_alg, comp_dense=K * W * H * 20 + W * H * 20, live_fragments=live,
+               commit_alg=commit_alg, commit_actual=commit_actual, voxel_bytes=voxel_bytes,
+               depth_range=[t_min, t_max])
+    # a band of rows of the 128 frames for the oracle's composite leg
+    band = None
+    if keep_host:
+        r0, r1 = H // 2 - 32, H // 2 + 32
+        band = dict(rgba=rgba[:, r0:r1].cpu().numpy(), depth=depth[:, r0:r1].cpu().numpy(), ids=np.array(ids),
+                    rows=(r0, r1))
+    for f in frames + [out, cf]:
+        f.release()
+    w.release()
+    del rgba, depth, sink
+    torch.cuda.empty_cache()
+    return res, host, band, cam, tf
+
+
+def copy_ceiling(torch, nbytes=2 << 30, reps=10):
+    """Plain device-to-device copy: achievable read+write HBM GB/s."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ms = _timed(torch, lambda: y.copy_(x), reps)
+    del x, y
+    torch.cuda.empty_cache()
+    return dict(bytes_read=nbytes, bytes_written=nbytes, ms=ms, GBps=2 * nbytes / ms / 1e6)
+
+
+# ---------------------------------------------------------------- secondary: 512^3 FP32, 2x2x2 bricks
+def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam):
+    w = dpr.World(dev, dims)
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH))
     for b in vol_bricks:
         w.add_brick(torch.from_numpy(b.data).to(dev.torch_device), b.lo, b.hi, b.ghost_lo, b.ghost_hi)
     w.commit()
@@ -128,116 +244,40 @@ def bench_main(args, dpr, torch, vol_bricks, dims, tf, cfg, cam):
     out = dpr.Frame(dev, W, H)
     total = _count_samples(dpr, dev, w, [cam], K)
     w.set_camera(cam)
-    # 8x8 item tiles (the library default, and the shape the autotuner picks on this
-    # workload -- see the batch section); fixed here so every timed launch, and every
-    # launch a profiler sees, has the same shape
-    tile = (8, 8)
-    w.set_batch_tile(*tile)
+    w.set_batch_tile(8, 8)
 
     def step():
-        w.commit()                                        # blocked copies + macrocell ranges
-        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)  # majorants follow
-        w.render_frame(out)                               # batched march + tile composite
+        w.commit()
+        w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
+        w.render_frame(out)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    march_ms, comp_ms = [], []
+    march_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
-        a, c = w.batch_timings()          # HIP events recorded around each kernel on the device stream
-        march_ms.append(a)
-        comp_ms.append(c)
+        march_ms.append(w.batch_timings()[0])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
-    # the plain per-brick path on the same frame: 8 render_partial launches + dpr_composite
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     parts = [dpr.Frame(dev, W, H) for _ in range(K)]
-
-    def plain():
-        for i, f in enumerate(parts):
-            w.render_partial(i, f)
-        dpr.composite(dev, parts, out, ids=list(range(K)))
-
-    plain()
-    torch.cuda.synchronize()
-    ms_plain = _timed(torch, plain, max(3, args.steps))
     ms_plain_march = _timed(torch, lambda: [w.render_partial(i, f) for i, f in enumerate(parts)], max(3, args.steps))
     live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
     comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
     ms_comp8 = _timed(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), max(3, args.steps))
-    res = dict(ms_per_step=ms_step, samples=total, tile=tile, march_ms=float(np.mean(march_ms)),
-               tile_comp_ms=float(np.mean(comp_ms)), ms_plain=ms_plain, ms_plain_march=ms_plain_march,
-               comp8_ms=ms_comp8, comp_bytes=comp_bytes)
     w.release()
     for f in parts + [out]:
         f.release()
-    return dev, res
-
-
-def bench_composite128(args, dpr, torch, dev):
-    """K = 128 sort-last composite at 3840x2160 (one GPU's share of a 128-rank frame):
-    the rendered frame of one rank's 2048x1536x1280 FP16 brick plus 127 synthetic
-    frames whose depth slabs lie in front of and behind that brick."""
-    from synth import make_volume_large, synthetic_frames
-    cfg = get_config("cfg5")
-    dims = cfg.dims
-    K, (W, H) = 128, cfg.image
-    cam = orbit_camera(dims, W, H)
-    # the brick's depth range from the camera: nearest point of the box, farthest corner
-    h = 1.0 / max(dims)
-    hi = np.array(dims, dtype=np.float64) * h
-    eye = np.array(cam.eye, dtype=np.float64)
-    t_min = float(np.linalg.norm(eye - np.clip(eye, 0.0, hi)))
-    t_max = float(max(np.linalg.norm(eye - np.array([x, y, z])) for x in (0.0, hi[0]) for y in (0.0, hi[1])
-                      for z in (0.0, hi[2])))
-    rgba = torch.empty((K, H, W, 4), dtype=torch.float32, device=dev.torch_device)
-    depth = torch.empty((K, H, W), dtype=torch.float32, device=dev.torch_device)
-    log("  rendering the 2048x1536x1280 FP16 brick at 3840x2160 (frame 0)")
-    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range, log_uniform=cfg.log_sigma)
-    vol = make_volume_large(dims, blobs, cfg.seeds["volume"], cfg.noise_amp, cfg.fbm_periods,
-                            device=dev.torch_device)
-    w = dpr.World(dev, dims)
-    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
-    w.add_brick(vol, (0, 0, 0), dims, (0, 0, 0), (0, 0, 0))
-    del vol
-    w.commit()
-    w.set_transfer_function(make_tf(cfg.seeds["tf"]), 0.0, 1.0, cfg.density)
-    w.set_camera(cam)
-    real = dpr.Frame(dev, W, H, rgba=rgba[0], depth=depth[0])
-    w.render_partial(0, real)
-    dev.sync()
-    w.release()
-    torch.cuda.empty_cache()
-    synthetic_frames(K - 1, W, H, t_min, t_max, cfg.seeds["frames"], dev.torch_device, rgba[1:], depth[1:])
-    frames = [real] + [dpr.Frame(dev, W, H, rgba=rgba[k], depth=depth[k]) for k in range(1, K)]
-    out = dpr.Frame(dev, W, H)
-    ids = list(np.random.default_rng(cfg.seeds["frames"]).permutation(K))
-    for _ in range(2):
-        dpr.composite(dev, frames, out, ids=ids)
-    torch.cuda.synchronize()
-    n = max(3, args.steps)
-    evs = [_events(torch) for _ in range(n)]
-    for e in evs:
-        e[0].record()
-        dpr.composite(dev, frames, out, ids=ids)
-        e[1].record()
-    torch.cuda.synchronize()
-    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    live = int(torch.isfinite(depth).sum().item())
-    real_live = int(torch.isfinite(depth[0]).sum().item())
-    alg = K * W * H * 4 + live * 16 + W * H * 20
-    dense = K * W * H * 20 + W * H * 20
-    for f in frames + [out]:
-        f.release()
-    del rgba, depth
-    torch.cuda.empty_cache()
-    gbs = alg / ms / 1e6
-    return dict(workload="K=128 sort-last composite, 3840x2160: the rendered frame of a 2048x1536x1280 FP16 "
-                         "brick + 127 synthetic RGBA32F+depth frames (depth slabs around the brick's range)",
-                ms=ms, algorithmic_bytes=alg, dense_bytes=dense, GBps=gbs, frac_hbm=gbs / HBM_PEAK_GBS,
-                real_frame_fragments=real_live, brick_depth_range=[t_min, t_max])
+    march = float(np.mean(march_ms))
+    return dict(workload="512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, step 0.5 "
+                         "voxel, ERT 0.99; per step: commit, majorants, batched march of the 8 bricks, tile composite",
+                logical_samples=total, ms_per_step=ms_step, msamples_step=total / ms_step / 1e3,
+                ms_batch_march=march, msamples_march=total / march / 1e3,
+                valu_frac=OPS_PER_SAMPLE * total / (march / 1e3) / 1e12 / VALU_PEAK_TOPS,
+                ms_plain_8_marches=ms_plain_march, batched_speedup_march=ms_plain_march / march,
+                composite_k8=dict(ms=ms_comp8, algorithmic_bytes=comp_bytes, GBps=comp_bytes / ms_comp8 / 1e6,
+                                  frac_hbm=comp_bytes / ms_comp8 / 1e6 / HBM_PEAK_GBS))
 
 
 def _timed(torch, fn, n):
@@ -520,64 +560,188 @@ def bench_train(args, dpr, torch, dev):
                 workspace_bytes=nb.value)
 
 
+# ---------------------------------------------------------------- CPU baseline (the oracle, not tuned)
+_W = {}
+
+
+def _worker_init(paths):
+    for k, p in paths.items():
+        _W[k] = np.load(p, mmap_mode="r")
+
+
+def _leg_render(job):
+    import oracle
+    dims, tf, prm, cam, px, py = job
+    _, _, n = oracle.render_brick(_W["volume"], (0, 0, 0), dims, (0, 0, 0), dims, tf, prm, cam, px, py)
+    return int(n.sum())
+
+
+def _leg_composite(job):
+    import oracle
+    c0, c1, ids = job
+    rgba = np.asarray(_W["band_rgba"][:, :, c0:c1])
+    depth = np.asarray(_W["band_depth"][:, :, c0:c1])
+    oracle.composite(rgba, depth, ids)
+    return 0
+
+
+def _leg_grad(job):
+    import oracle
+    dims, tf, prm, cam, px, py = job
+    target = [np.zeros((px.size, 4))]
+    oracle.loss_and_grad(np.asarray(_W["train_volume"]), dims, tf, prm, [cam], target, pixels=[(px, py)],
+                         n_elems=4 * px.size)
+    return 0
+
+
+def _segments(cam, dims, step_voxels, px, py):
+    """Lattice segments of positive length per ray through the whole volume (ERT off)."""
+    import oracle
+    h = 1.0 / max(dims)
+    dt = step_voxels * h
+    o, d = oracle.camera_rays(cam, px, py)
+    t_in, t_out, hit = oracle.clip_box(o, d, np.zeros(3), np.array(dims, dtype=np.float64) * h)
+    s0, s1 = np.floor(t_in / dt), np.ceil(t_out / dt) - 1.0
+    first = np.minimum((s0 + 1) * dt, t_out) - np.maximum(s0 * dt, t_in) > 0
+    last = np.minimum((s1 + 1) * dt, t_out) - np.maximum(s1 * dt, t_in) > 0
+    n = (s1 - s0 + 1) - (~first) - ((~last) & (s1 > s0))
+    return int(np.sum(np.where(hit, np.maximum(n, 0), 0)))
+
+
+def cpu_baseline(args, host_volume, band, cam5, tf5):
+    import oracle
+    from synth import fibonacci_cameras
+    cores = min(16, len(os.sched_getaffinity(0)))
+    shm = os.path.join("/dev/shm" if os.path.isdir("/dev/shm") else "/tmp", f"dpr_bench_{os.getpid()}")
+    os.makedirs(shm, exist_ok=True)
+    try:
+        cfg5, cfg4 = get_config("cfg5"), get_config("cfg4")
+        paths = {"volume": os.path.join(shm, "volume.npy"), "band_rgba": os.path.join(shm, "band_rgba.npy"),
+                 "band_depth": os.path.join(shm, "band_depth.npy"), "train_volume": os.path.join(shm, "train.npy")}
+        np.save(paths["volume"], host_volume)
+        np.save(paths["band_rgba"], band["rgba"])
+        np.save(paths["band_depth"], band["depth"])
+        blobs = make_blobs(cfg4.dims, cfg4.seeds["volume"], cfg4.n_blobs, cfg4.s_range, cfg4.a_range)
+        np.save(paths["train_volume"], make_volume_small(cfg4.dims, blobs, cfg4.seeds["volume"], cfg4.noise_amp))
+        legs = {}
+        with mp.get_context("spawn").Pool(cores, initializer=_worker_init, initargs=(paths,)) as pool:
+            pool.map(abs, range(4 * cores))   # workers started and initialised before any leg is timed
+            # render: every stride-th pixel in x and y of the headline frame
+            s = args.cpu_stride
+            py, px = np.mgrid[0:cam5.height:s, 0:cam5.width:s]
+            px, py = px.ravel(), py.ravel()
+            prm = oracle.RenderParams(cfg5.step_voxels, cfg5.ert, cfg5.density)
+            nj = 8 * cores   # interleaved pixels, so every job gets its share of the rays that hit the brick
+            jobs = [(cfg5.dims, tf5, prm, cam5, px[j::nj], py[j::nj]) for j in range(nj)]
+            t0 = time.perf_counter()
+            samples = sum(pool.map(_leg_render, jobs, chunksize=1))
+            dt = time.perf_counter() - t0
+            render = dict(value=samples / dt / 1e6, unit="Msamples/s", seconds=dt, samples=samples,
+                          sample=f"every {s}th pixel in x and y of the 3840x2160 frame ({px.size} rays) through the "
+                                 f"2048x1536x1280 FP16 brick, ERT 0.99: {samples} logical samples")
+            # composite: the 128 frames on a band of rows
+            K, R, Wd = band["depth"].shape
+            live = int(np.isfinite(band["depth"]).sum())
+            cols = np.array_split(np.arange(Wd), 4 * cores)
+            t0 = time.perf_counter()
+            pool.map(_leg_composite, [(int(c[0]), int(c[-1]) + 1, band["ids"]) for c in cols], chunksize=1)
+            dt = time.perf_counter() - t0
+            alg = K * R * Wd * 4 + live * 16 + R * Wd * 20
+            legs["composite_k128"] = dict(value=alg / dt / 1e9, unit="GB/s", seconds=dt, algorithmic_bytes=alg,
+                                          sample=f"rows {band['rows'][0]}..{band['rows'][1] - 1} of the 128 "
+                                                 f"3840x2160 frames ({R * Wd} pixels)")
+            # gradient: one 512x512 camera of the 256^3 training volume, every gs-th pixel
+            gs = 4
+            cam4 = fibonacci_cameras(cfg4.dims, cfg4.n_cams, *cfg4.image)[0]
+            gy, gx = np.mgrid[0:cam4.height:gs, 0:cam4.width:gs]
+            gx, gy = gx.ravel(), gy.ravel()
+            prm4 = oracle.RenderParams(cfg4.step_voxels, 1.0, cfg4.density)
+            tf4 = make_tf(cfg4.seeds["tf"])
+            gjobs = [(cfg4.dims, tf4, prm4, cam4, gx[j::nj], gy[j::nj]) for j in range(nj)]
+            t0 = time.perf_counter()
+            pool.map(_leg_grad, gjobs, chunksize=1)
+            dt = time.perf_counter() - t0
+            gsamples = _segments(cam4, cfg4.dims, cfg4.step_voxels, gx, gy)
+            legs["gradient_cfg4"] = dict(value=gsamples / dt / 1e6, unit="Msamples/s (forward + backward)",
+                                         seconds=dt, samples=gsamples,
+                                         sample=f"every {gs}th pixel in x and y of one 512x512 camera ({gx.size} "
+                                                f"rays) of the 256^3 FP32 training volume, ERT off, L2 loss "
+                                                f"against a zero target")
+        return dict(value=render["value"], unit="Msamples/s", cores=cores, kind="oracle", sample=render["sample"],
+                    seconds=render["seconds"], legs=legs,
+                    how="FP64 numpy oracle over a spawned pool of host processes reading the inputs from shared "
+                        "memory")
+    finally:
+        shutil.rmtree(shm, ignore_errors=True)
+
+
+def roofline_of(r, copy):
+    """Roofline of the step's dominant kernel (the longest of commit, march and
+    K = 128 composite, by HIP-event time)."""
+    ph = r["phases"]
+    cands = {"batch_march_kernel": ph["batch_march"], "commit_kernel": ph["commit"],
+             "composite_fast_kernel": ph["composite_k128"]}
+    kern = max(cands, key=cands.get)
+    ms = cands[kern]
+    if kern == "batch_march_kernel":
+        work = "3840x2160 march of the 2048x1536x1280 FP16 brick, ERT 0.99"
+        achieved = OPS_PER_SAMPLE * r["samples"] / (ms / 1e3) / 1e12
+        gather = OPS_PER_SAMPLE * r["samples"] / (r["ms_gather_probe"] / 1e3) / 1e12
+        peak, bound = (VALU_PEAK_TOPS, "alu") if VALU_PEAK_TOPS <= gather else (gather, "gather")
+        rf = dict(bound=bound, achieved=achieved, peak=peak, unit="Tops/s", frac=achieved / peak,
+                  per_unit=f"{OPS_PER_SAMPLE} VALU lane-op slots per logical sample x {r['samples']} samples",
+                  ceilings=dict(valu_Tops=VALU_PEAK_TOPS, gather_Tops=gather,
+                                valu_Msamples=VALU_PEAK_TOPS * 1e6 / OPS_PER_SAMPLE,
+                                gather_Msamples=r["samples"] / r["ms_gather_probe"] / 1e3,
+                                gather_probe_ms=r["ms_gather_probe"]),
+                  frac_of_valu_peak=achieved / VALU_PEAK_TOPS)
+    elif kern == "commit_kernel":
+        work = "commit of the 2048x1536x1280 FP16 brick"
+        achieved = r["commit_alg"] / ms / 1e6
+        rf = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                  per_unit="every stored voxel read once and written once (2 + 2 B) + 8 B per macrocell",
+                  frac_of_copy_ceiling=achieved / copy["GBps"])
+    else:
+        work = "K=128 composite at 3840x2160"
+        achieved = r["comp_alg"] / ms / 1e6
+        rf = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                  per_unit="per pixel: 128 depths (4 B), RGBA of live fragments (16 B), 20 B written",
+                  frac_of_copy_ceiling=achieved / copy["GBps"])
+    c = stored_counters(kern, work)
+    rf.update(kernel=kern, workload=work, ms_per_launch=ms,
+              traffic=None if c is None else c["traffic_bytes_per_launch"],
+              counters=None if c is None else {k: v for k, v in c.items() if k not in ("kernel", "workload")})
+    return rf
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-stride", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batch,cfg3,train,composite128,deep,iso,path")
-    ap.add_argument("--main-only", action="store_true", help="only the default workload, no extra sections")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="run one plain 256 MiB device-to-device copy first (scales HBM byte counters)")
+    ap.add_argument("--sections", default="cfg2,batch,cfg3,train,iso,path,deep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the library renders on one GPU; runs on several GPUs are not supported",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (one rank's share of the data-parallel run); "
+                                   "runs on several GPUs are not supported", "n_gpus": args.gpus}))
         sys.exit(2)
-
-    cfg = get_config("cfg2")
-    dims = cfg.dims
-    log("generating the 512^3 volume and its 8 bricks")
-    blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
-    vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
-    tf = make_tf(cfg.seeds["tf"])
-    cam = orbit_camera(dims, *cfg.image)
-    boxes = even_split(dims, cfg.parts)
-    bricks = [extract_brick(vol, dims, lo, hi, 1) for lo, hi in boxes]
-    del vol
-
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        cores = min(16, len(os.sched_getaffinity(0)))
-        log(f"CPU oracle baseline on {cores} cores")
-        cpu = cpu_baseline(bricks, dims, tf, oracle.RenderParams(cfg.step_voxels, cfg.ert, cfg.density), cam,
-                           args.cpu_stride, cores)
-        log(f"CPU oracle: {cpu['value']:.2f} Msamples/s")
+    secs = [s for s in args.sections.split(",") if s and s != "none"]
 
     import torch
     import paper_2407_00179_amd as dpr
-    if args.copy_calibration:
-        x = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
-        del x, y
-    log("GPU: default workload")
-    dev, r = bench_main(args, dpr, torch, bricks, dims, tf, cfg, cam)
-    msamples = r["samples"] / (r["ms_per_step"] / 1e3) / 1e6
-    achieved = OPS_PER_SAMPLE * r["samples"] / (r["march_ms"] / 1e3) / 1e12
-    counters_valid = march_sources_sha256() == MARCH_COUNTERS["sources_sha256"]
-    traffic = MARCH_COUNTERS["traffic_bytes_per_launch"] if counters_valid else None
-    # share of the VALU issue slots the launch used, from the measured instruction count
-    valu_issue_frac = (MARCH_COUNTERS["valu_lane_instr_per_sample"] * r["samples"] / (r["march_ms"] / 1e3)
-                       / 1e12 / VALU_PEAK_TOPS) if counters_valid else None
+    dev = dpr.Device(0)
+    log("GPU: copy ceiling")
+    copy = copy_ceiling(torch)
+    log("GPU: one rank's share of a 128-rank run (headline)")
+    r, host, band, cam5, tf5 = bench_rank_share(args, dpr, torch, dev, keep_host=not args.no_cpu)
+    ph = r["phases"]
+    value = r["samples"] / (r["ms_per_step"] / 1e3) / 1e6
+    cfg5 = get_config("cfg5")
     line = {
-        "metric": "Msamples/s (logical ray-march samples, render + composite)",
-        "value": msamples,
+        "metric": "Msamples/s + composite GB/s (% HBM peak) per GPU; backward/forward time ratio",
+        "value": value,
         "unit": "Msamples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -586,29 +750,52 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16 storage, f32 math",
         "data": "synthetic",
-        "config": {"workload": "512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, "
-                               "step 0.5 voxel, ERT 0.99, 16^3 macrocells; per step: commit (blocked copies + "
-                               "macrocell ranges), majorants, batched march of the 8 bricks, tile composite",
-                   "logical_samples_per_step": r["samples"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "batch_march_kernel", "ms_per_launch": r["march_ms"],
-                     "ops_per_sample": OPS_PER_SAMPLE, "valu_issue_frac": valu_issue_frac},
-        "phases_ms": {"batch_march": r["march_ms"], "tile_composite": r["tile_comp_ms"]},
-        "batch_tile": r["tile"],
-        "plain_per_brick": {"ms_render_and_composite": r["ms_plain"], "ms_8_marches": r["ms_plain_march"],
-                            "msamples": r["samples"] / r["ms_plain"] / 1e3,
-                            "batched_speedup_march": r["ms_plain_march"] / r["march_ms"]},
-        "composite_k8": {"ms": r["comp8_ms"], "algorithmic_bytes": r["comp_bytes"],
-                         "GBps": r["comp_bytes"] / r["comp8_ms"] / 1e6,
-                         "frac_hbm": r["comp_bytes"] / r["comp8_ms"] / 1e6 / HBM_PEAK_GBS},
-        "cpu_baseline": cpu,
+        "config": {"workload": "one rank's share of a 128-rank large-volume run: 2048x1536x1280 FP16 blob+fBm brick "
+                               "(8.05 GB) -> 3840x2160 partial frame (step 0.5 voxel, ERT 0.99, 16^3 macrocells), "
+                               "then K=128 sort-last composite with 127 synthetic RGBA32F+depth frames; per step: "
+                               "commit (blocked copy + macrocell ranges), majorants, batched march, tile composite, "
+                               "K=128 composite",
+                   "logical_samples_per_step": r["samples"], "hit_pixels": r["hit_pixels"],
+                   "image": list(cfg5.image), "brick": list(cfg5.dims), "batch_tile": list(r["tile"])},
+        "roofline": roofline_of(r, copy),
+        "phases_ms": ph,
+        "render_msamples": r["samples"] / ph["batch_march"] / 1e3,
+        "commit": {"ms": ph["commit"], "algorithmic_bytes": r["commit_alg"],
+                   "GBps": r["commit_alg"] / ph["commit"] / 1e6,
+                   "frac_hbm": r["commit_alg"] / ph["commit"] / 1e6 / HBM_PEAK_GBS,
+                   "bytes_moved": r["commit_actual"], "GBps_moved": r["commit_actual"] / ph["commit"] / 1e6,
+                   "frac_copy_ceiling": r["commit_alg"] / ph["commit"] / 1e6 / copy["GBps"],
+                   "layout": "8^3 blocks of 2-byte FP16 voxels (the pair layout is kept for bricks below 4 GiB)"},
+        "composite_k128": {"ms": ph["composite_k128"], "algorithmic_bytes": r["comp_alg"],
+                           "dense_bytes": r["comp_dense"], "GBps": r["comp_alg"] / ph["composite_k128"] / 1e6,
+                           "frac_hbm": r["comp_alg"] / ph["composite_k128"] / 1e6 / HBM_PEAK_GBS,
+                           "frac_copy_ceiling": r["comp_alg"] / ph["composite_k128"] / 1e6 / copy["GBps"],
+                           "live_fragments": r["live_fragments"], "brick_depth_range": r["depth_range"]},
+        "plain_per_brick": {"ms_march": r["ms_plain_march"],
+                            "msamples": r["samples"] / r["ms_plain_march"] / 1e3,
+                            "batched_speedup_march": r["ms_plain_march"] / ph["batch_march"],
+                            "identical_bits": r["identical_to_plain"]},
+        "copy_ceiling": copy,
+        "cpu_baseline": None,
     }
-    secs = [] if args.main_only else [s for s in args.sections.split(",") if s]
+    cfg = get_config("cfg2")
+    dims = cfg.dims
+    tf = make_tf(cfg.seeds["tf"])
+    cam = orbit_camera(dims, *cfg.image)
+    bricks = None
+    if any(s in secs for s in ("cfg2", "batch", "iso")):
+        log("generating the 512^3 volume and its 8 bricks")
+        blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
+        vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
+        bricks = [extract_brick(vol, dims, lo, hi, 1) for lo, hi in even_split(dims, cfg.parts)]
+        del vol
+    if "cfg2" in secs:
+        log("GPU: 512^3 FP32 2x2x2 step")
+        line["step_cfg2"] = bench_cfg2_step(args, dpr, torch, dev, bricks, dims, tf, cfg, cam)
     if "batch" in secs:
-        log("GPU: batched renderer on the default workload")
+        log("GPU: batched renderer vs plain launches on the 512^3 2x2x2 workload")
         w = dpr.World(dev, dims)
         w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, 0))
         for b in bricks:
@@ -624,7 +811,7 @@ def main():
         log("GPU: differentiable render forward/backward")
         line["train_cfg4"] = bench_train(args, dpr, torch, dev)
     if "iso" in secs:
-        log("GPU: iso-surface on the default workload")
+        log("GPU: iso-surface on the 512^3 2x2x2 workload")
         line["iso_cfg2"] = bench_iso(args, dpr, torch, dev, bricks, dims, tf, cfg, cam)
     if "path" in secs:
         log("GPU: data-parallel path tracing")
@@ -632,10 +819,11 @@ def main():
     if "deep" in secs:
         log("GPU: deep frames of an interleaved 8-rank partition")
         line["deep_8ranks"] = bench_deep(args, dpr, torch, dev)
-    if "composite128" in secs:
-        log("GPU: K=128 composite at 3840x2160")
-        line["composite_k128"] = bench_composite128(args, dpr, torch, dev)
     dev.release()
+    if not args.no_cpu:
+        log("CPU oracle baseline (render, K=128 composite and gradient legs)")
+        line["cpu_baseline"] = cpu_baseline(args, host, band, cam5, tf5)
+        log(f"CPU oracle: {line['cpu_baseline']['value']:.2f} Msamples/s on {line['cpu_baseline']['cores']} cores")
     print(json.dumps(line), flush=True)
 
 

@@ -63,8 +63,16 @@ typedef enum { DPR_F32 = 0, DPR_F16 = 1 } dpr_dtype;
 #define DPR_FLAG_PLAIN 0x2u      /* one plain launch per (camera, brick) + composite  */
 #define DPR_FLAG_NO_GRAPH 0x4u   /* batched paths: enqueue directly, no graph replay */
 /* render parameter: form voxel offsets in 64 bits for every brick (automatic for
- * bricks whose blocked array is 4 GiB or more); the results are identical       */
+ * bricks whose blocked array is 4 GiB or more); the results are identical.  For
+ * FP16 bricks it implies DPR_FLAG_F16_HALVES, and changing it un-commits the
+ * world (the next dpr_world_commit lays the bricks out again)                  */
 #define DPR_FLAG_WIDE_OFFSETS 0x8u
+/* render parameter read by dpr_world_commit: store the world's FP16 bricks as
+ * 2-byte voxels, addressed with 64-bit offsets (automatic once some brick's
+ * voxel-pair copy would reach 4 GiB), instead of 4-byte voxel pairs: half the
+ * memory and half the cache lines per sample, more loads per sample; the results
+ * are identical.  Changing it un-commits the world.                             */
+#define DPR_FLAG_F16_HALVES 0x10u
 
 typedef struct dpr_device_t* dpr_device; /* one GPU + one HIP stream              */
 typedef struct dpr_world_t* dpr_world;   /* this rank's bricks + TF + camera      */
@@ -84,7 +92,7 @@ typedef struct {
  * ert_threshold: stop a ray once 1 - T >= threshold; >= 1 disables.
  * macrocell_cells: macrocell edge in cells (power of two in [2, 64]).
  * flags: DPR_FLAG_NO_SKIP, DPR_FLAG_PLAIN, DPR_FLAG_NO_GRAPH (dpr_render_frame),
- * DPR_FLAG_WIDE_OFFSETS. */
+ * DPR_FLAG_WIDE_OFFSETS, DPR_FLAG_F16_HALVES. */
 typedef struct {
   float step_voxels;
   float ert_threshold;
@@ -122,8 +130,10 @@ void dpr_world_release(dpr_world);
  * brick_id receives the brick's index (0, 1, ...), which is also its intrinsic
  * fragment id for compositing.  Adding a brick un-commits the world.
  * Device memory per brick: the linear copy (2 or 4 bytes per stored voxel) plus,
- * after commit, the blocked copy at 4 bytes per voxel for either dtype (an F16
- * element holds a voxel and its +x neighbour) and the macrocell arrays.         */
+ * after commit, the blocked copy at 4 bytes per voxel (FP32, or FP16 stored as
+ * voxel pairs: an element holds a voxel and its +x neighbour) or 2 bytes per
+ * voxel (FP16 stored as halves: DPR_FLAG_F16_HALVES, or automatically when the
+ * pair copy would reach 4 GiB) and the macrocell arrays.                        */
 dpr_status dpr_world_add_brick(dpr_world, const void* voxels, dpr_dtype dtype, int voxels_on_device,
                                const int64_t owned_lo[3], const int64_t owned_hi[3],
                                const int32_t ghost_lo[3], const int32_t ghost_hi[3], int32_t* brick_id);
@@ -267,6 +277,20 @@ dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
  * device stream around each kernel.  Synchronises.  DPR_ERR_INVALID_STATE when
  * the last batched render was a graph replay (or there was none).             */
 dpr_status dpr_batch_timings(dpr_world, float* march_ms, float* composite_ms);
+
+/* ---------------------------------------------------------------- measurement */
+/* Gather ceiling of the local render (a roofline probe, not part of the
+ * paradigm): for every pixel of the world's camera, issue the voxel loads that
+ * dpr_render_partial makes for brick `brick_id` over the first counts[p] logical
+ * samples of the pixel's ray (the same lattice points, the same macrocell skip
+ * rule, the same 8-voxel footprints), with no transfer function, no compositing
+ * and no dependence between consecutive samples (each ray's samples are cut
+ * into slices that separate threads load).  counts (int32) and sink (float; a
+ * checksum of the loaded values is added to each pixel's entry) are device
+ * arrays of width * height elements, row-major, typically the sample counts a render with a count buffer
+ * attached wrote (dpr_frame_attach_counts).  Enqueued on the device stream; the
+ * caller times it.                                                              */
+dpr_status dpr_measure_gather(dpr_world, int32_t brick_id, const int32_t* counts, float* sink);
 
 /* ---------------------------------------------------------------- deep frames */
 /* Section 5.1.1 lets a rank emit possibly several RGBA-z fragments per pixel;

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _native as N
-from ._native import (DprError, F16, F32, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, FLAG_WIDE_OFFSETS,  # noqa: F401
+from ._native import (DprError, F16, F32, FLAG_F16_HALVES, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, FLAG_WIDE_OFFSETS,  # noqa: F401
                       check, lib)
 
 __all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_camera", "render_train",
@@ -257,6 +257,12 @@ class World:
 
     def render_frame(self, frame: Frame):
         check(lib.dpr_render_frame(self.h, frame.h))
+
+    def measure_gather(self, brick_id, counts, sink):
+        """Gather-ceiling probe: the march's loads for the first counts[p] logical
+        samples of every pixel (device int32 / float tensors of the camera's size)."""
+        check(lib.dpr_measure_gather(self.h, int(brick_id), C.c_void_p(counts.data_ptr()),
+                                     C.c_void_p(sink.data_ptr())))
 
     def render_deep(self, rank, deep: "DeepFrame"):
         """Every brick of this world into ``deep`` (fragment ids rank * 65536 + brick)."""

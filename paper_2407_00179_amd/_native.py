@@ -28,7 +28,7 @@ OK = 0
 STATUS = {0: "DPR_OK", -1: "DPR_ERR_INVALID_ARGUMENT", -2: "DPR_ERR_INVALID_STATE", -3: "DPR_ERR_OUT_OF_MEMORY",
           -4: "DPR_ERR_DEVICE", -5: "DPR_ERR_UNSUPPORTED"}
 F32, F16 = 0, 1
-FLAG_NO_SKIP, FLAG_PLAIN, FLAG_NO_GRAPH, FLAG_WIDE_OFFSETS = 0x1, 0x2, 0x4, 0x8
+FLAG_NO_SKIP, FLAG_PLAIN, FLAG_NO_GRAPH, FLAG_WIDE_OFFSETS, FLAG_F16_HALVES = 0x1, 0x2, 0x4, 0x8, 0x10
 
 
 class DprError(RuntimeError):
@@ -90,6 +90,7 @@ _SIGS = {
     "dpr_frame_release": ([P], None),
     "dpr_render_partial": ([P, C.c_int32, P], C.c_int),
     "dpr_composite": ([P, P, P, C.c_int32, P], C.c_int),
+    "dpr_measure_gather": ([P, C.c_int32, P, P], C.c_int),
     "dpr_composite_noalloc": ([P, P, P, C.c_int32, P], C.c_int),
     "dpr_render_frame": ([P, P], C.c_int),
     "dpr_render_batch": ([P, P, C.c_int32, P, C.c_uint32], C.c_int),

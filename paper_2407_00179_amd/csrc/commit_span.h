@@ -8,7 +8,7 @@
 
 namespace dpr {
 
-constexpr int kCmCols = 320;  // x-voxels a commit workgroup may load (5 chunks of 64)
+constexpr int kCmCols = 384;  // x-voxels a commit workgroup may load (3 chunks of 128)
 
 // Window, write core and loaded range of macrocells [m0, m1) along one axis of n
 // stored voxels whose first owned voxel is stored at g (align: 4 for x-runs, 2

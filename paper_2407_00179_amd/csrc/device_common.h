@@ -8,6 +8,14 @@
 namespace dpr {
 
 constexpr int kBlockEdge = 8;         // bricks are stored as 8^3-voxel blocks
+// FP16 bricks are stored in one of two layouts, chosen per world at commit:
+// 4-byte elements holding the voxel pair (x, x + 1) -- one load per trilinear
+// x-pair, the faster layout while gathers mostly hit the cache -- or 2-byte
+// elements holding one voxel -- half the bytes, so half the cache lines per
+// sample and half the memory -- once a brick's pair copy would reach 4 GiB.  The
+// 2-byte layout always goes with 64-bit voxel offsets, so the kernels' WIDE
+// variants read it and their narrow variants read pairs.
+constexpr uint64_t kF16HalvesFrom = 1ull << 32;  // pair-copy bytes from which FP16 bricks store halves
 constexpr int kBlockVoxels = 512;
 constexpr int kMaxTF = 1024;          // transfer-function entries held in LDS
 
@@ -30,7 +38,8 @@ struct BrickG {
   const float* majorant;  // per macrocell, x fastest (may be null when skipping is off)
   int mdim[3];            // macrocell grid
   int mc_shift;           // log2(macrocell edge)
-  int wide;               // blocked array of 4 GiB or more (64-bit voxel offsets)
+  int wide;               // 64-bit voxel offsets (blocked array of 4 GiB or more, an FP16 brick
+                          // stored as 2-byte voxels, or asked for); else 32-bit byte offsets
 };
 
 // Scene-wide render constants.
@@ -76,8 +85,8 @@ template <int SH>
 __device__ __forceinline__ uint32_t blkb_z(int k, uint32_t bsz_b) {
   return (uint32_t)(k >> 3) * bsz_b + (blk_z(k & 7, 0u) << SH);
 }
-template <typename T>
-__device__ __forceinline__ float load_voxel_b(const void* base, uint32_t boff) {
+template <typename T, typename Off>
+__device__ __forceinline__ float load_voxel_b(const void* base, Off boff) {
   using GC = const char __attribute__((address_space(1)))*;
   const GC q = (GC)base + boff;
   if constexpr (sizeof(T) == 2)
@@ -88,9 +97,13 @@ __device__ __forceinline__ float load_voxel_b(const void* base, uint32_t boff) {
 
 // An F32 voxel at byte offset boff and the element after it in memory, in one
 // load aligned to 4 bytes only.  A blocked array carries kPairSlack spare bytes so
-// the element after its last voxel can be read.
+// the element after its last voxel can be read.  Off: uint32_t byte offsets for
+// blocked arrays below 4 GiB, uint64_t above; the pointer is in the global address
+// space either way, so the load is a global (not flat) load and waits only on the
+// vector-memory counter.
 constexpr size_t kPairSlack = 64;
-__device__ __forceinline__ float2 load_pair_f32(const void* base, uint32_t boff) {
+template <typename Off>
+__device__ __forceinline__ float2 load_pair_f32(const void* base, Off boff) {
   typedef float F2 __attribute__((ext_vector_type(2), aligned(4)));
   using GC = const char __attribute__((address_space(1)))*;
   const F2 f = *(const F2 __attribute__((address_space(1)))*)((GC)base + boff);
@@ -102,15 +115,18 @@ __device__ __forceinline__ float2 unpack_pair_f16(uint32_t u) {
   return make_float2(__half2float(__ushort_as_half((unsigned short)(u & 0xffffu))),
                      __half2float(__ushort_as_half((unsigned short)(u >> 16))));
 }
-__device__ __forceinline__ float2 load_pair_f16(const void* base, uint32_t boff) {
+template <typename Off>
+__device__ __forceinline__ float2 load_pair_f16(const void* base, Off boff) {
   using GC = const char __attribute__((address_space(1)))*;
   return unpack_pair_f16(*(const uint32_t __attribute__((address_space(1)))*)((GC)base + boff));
 }
 
-template <typename T> __device__ __forceinline__ float load_voxel(const T* p, uint32_t off);
-template <> __device__ __forceinline__ float load_voxel<float>(const float* p, uint32_t off) { return p[off]; }
-template <> __device__ __forceinline__ float load_voxel<__half>(const __half* p, uint32_t off) {
-  return __half2float(p[off]);
+// Element i of an array in device memory, read with a global (not flat) load:
+// pointers fetched from memory lose their address space, and a flat load also
+// holds back the LDS counter that transfer-function lookups wait on.
+template <typename T>
+__device__ __forceinline__ T ld_global(const T* p, size_t i) {
+  return ((const T __attribute__((address_space(1)))*)p)[i];
 }
 
 // Ray through pixel (px, py); returns the unit direction.

@@ -78,6 +78,75 @@ __global__ __launch_bounds__(256) void march_kernel(SceneG sc, BrickG b, CamG ca
   if (out_count) out_count[p] = r.n;
 }
 
+// Gather ceiling of the march (a measurement, not part of rendering): per pixel,
+// the march's own lattice sample points over its first n logical samples (n
+// from a march's per-pixel sample counts), the same skip rule and the same
+// 8-voxel loads, but no transfer function, no compositing and no dependence
+// between samples.  Each ray's samples are cut into kProbeSlots contiguous slices
+// handled by different threads (grid y), and every thread keeps the loads of
+// kProbeUnroll samples in flight, so no ray's length bounds the probe.  A skipped
+// sample (macrocell majorant 0) re-reads the previous point, which the cache
+// already holds.  The sum of the loaded values is added to sink[p].
+constexpr int kProbeUnroll = 4;
+constexpr int kProbeSlots = 16;
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(256) void gather_probe_kernel(SceneG sc, BrickG b, CamG cam,
+                                                           const int* __restrict__ counts, float* __restrict__ sink,
+                                                           int tiles_x, int n_tiles) {
+  // consecutive tiles go to consecutive workgroups, so the XCDs (dealt workgroups
+  // in turn) share every part of the screen, however little of it the brick covers
+  const int tile = blockIdx.x;
+  if (tile >= n_tiles) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int px = (tile % tiles_x) * 16 + (wave & 1) * 8 + (lane & 7);
+  const int py = (tile / tiles_x) * 16 + (wave >> 1) * 8 + (lane >> 3);
+  if (px >= cam.W || py >= cam.H) return;
+  const size_t p = (size_t)py * cam.W + px;
+  const int n = counts[p];
+  const int slot = blockIdx.y;
+  const int k0 = (int)((int64_t)n * slot / kProbeSlots), k1 = (int)((int64_t)n * (slot + 1) / kProbeSlots);
+  float acc = 0.f;
+  double d[3];
+  camera_ray(cam, px, py, d);
+  RayState r;
+  if (k1 > k0 && ray_begin(sc, b, cam.eye, d, r)) {
+    const int64_t half = 0x80000000ll;
+    int64_t last[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) last[a] = r.p[a] + (int64_t)k0 * r.dp[a];
+    for (int i = k0; i < k1; i += kProbeUnroll) {
+      int64_t q[kProbeUnroll][3];
+#pragma unroll
+      for (int u = 0; u < kProbeUnroll; ++u) {
+        const int k = min(i + u, k1 - 1);
+        int m[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          q[u][a] = r.p[a] + (int64_t)k * r.dp[a];
+          const int cell = (int)((q[u][a] + half) >> 32);
+          m[a] = min(max((cell - b.olo[a]) >> b.mc_shift, 0), b.mdim[a] - 1);
+        }
+        const bool empty = b.majorant && ld_global(b.majorant, (m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]) == 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          q[u][a] = empty ? last[a] : q[u][a];
+          last[a] = q[u][a];
+        }
+      }
+      float v[kProbeUnroll];
+#pragma unroll
+      for (int u = 0; u < kProbeUnroll; ++u) {
+        Gather<T> g;
+        gather<T, WIDE>(sc, b, q[u], g);
+        v[u] = ((g.v[0] + g.v[1]) + (g.v[2] + g.v[3])) + ((g.v[4] + g.v[5]) + (g.v[6] + g.v[7]));
+      }
+#pragma unroll
+      for (int u = 0; u < kProbeUnroll; ++u) acc += v[u];
+    }
+  }
+  if (k1 > k0) atomicAdd(&sink[p], acc);
+}
+
 // ------------------------------------------------------------------ host launchers
 hipError_t launch_majorants(const MajJobs& jobs, const float4* tf, int ntf, float lo, float hi, hipStream_t st) {
   long long total = 0;
@@ -110,6 +179,21 @@ hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, cons
     by_skip(__half{});
   else
     by_skip(float{});
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_probe(const SceneG& sc, const BrickG& b, const CamG& cam, bool f16, const int* counts,
+                               float* sink, hipStream_t st) {
+  int tx = (cam.W + 15) / 16, ty = (cam.H + 15) / 16;
+  int n_tiles = tx * ty;
+  int nb = ((n_tiles + 7) / 8) * 8;
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(nb, kProbeSlots), dim3(256), 0, st, sc, b, cam, counts, sink, tx, n_tiles);
+  };
+  if (f16)
+    b.wide ? go(gather_probe_kernel<__half, true>) : go(gather_probe_kernel<__half, false>);
+  else
+    b.wide ? go(gather_probe_kernel<float, true>) : go(gather_probe_kernel<float, false>);
   return hipGetLastError();
 }
 

@@ -7,6 +7,9 @@
 
 namespace dpr {
 
+// Bytes past the end of a brick's linear copy that the commit may read (its run
+// loads cover whole 8-voxel runs from an aligned dword); allocated, never used.
+constexpr size_t kLinearSlack = 32;
 // One brick of a commit: its linear stored copy, device view (view.data: the
 // blocked copy to fill) and macrocell ranges to fill.
 struct McBrick {
@@ -14,6 +17,7 @@ struct McBrick {
   BrickG view;
   float2* ranges;
   bool f16;
+  bool half16;  // FP16 blocked copy of 2-byte voxels (else 4-byte voxel pairs)
 };
 // Blocked copy and macrocell ranges of several bricks in one pass over their
 // linear stored copies.
@@ -33,6 +37,10 @@ struct MajJobs {
 hipError_t launch_majorants(const MajJobs& jobs, const float4* tf, int ntf, float lo, float hi, hipStream_t st);
 hipError_t launch_march(const SceneG& sc, const BrickG& b, const CamG& cam, const float4* tf, bool f16, bool skip,
                         float4* rgba, float* depth, int* count, hipStream_t st);
+// Gather ceiling of the march (measurement): the march's loads for the first
+// counts[p] logical samples of every pixel, with no dependence between samples.
+hipError_t launch_gather_probe(const SceneG& sc, const BrickG& b, const CamG& cam, bool f16, const int* counts,
+                               float* sink, hipStream_t st);
 
 // Composite table: per fragment list entry, the frame pointers and the rank of
 // its intrinsic id among the k ids (ties in depth are broken by that rank).

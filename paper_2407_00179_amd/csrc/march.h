@@ -108,14 +108,18 @@ __device__ __forceinline__ int steps_inside(int64_t p, int64_t dp, int64_t b_lo,
   return q < (int64_t)cap ? (int)q : cap;
 }
 
-__device__ __forceinline__ void clamp_axis(int64_t p, int n, int slo, int sdim, int& l, float& f) {
+// Voxel index (stored, relative to the brick) and fraction along one axis of a
+// 32.32 fixed-point sample point, clamped to the global domain [0, n - 1].
+__device__ __forceinline__ int axis_index(int64_t p, int n, int slo, int sdim) {
   const int hi = (int)(p >> 32);
-  float fr = (float)(uint32_t)(p & 0xffffffffll) * (1.0f / 4294967296.0f);
-  fr = (hi < 0) ? 0.f : ((hi > n - 2) ? 1.f : fr);
   const int i0 = min(max(hi, 0), n - 2);
   // commit guarantees i0 - slo lies in [0, sdim - 2]; the clamp only guards memory
-  l = min(max(i0 - slo, 0), sdim - 2);
-  f = fr;
+  return min(max(i0 - slo, 0), sdim - 2);
+}
+__device__ __forceinline__ float axis_frac(int64_t p, int n) {
+  const int hi = (int)(p >> 32);
+  const float fr = (float)(uint32_t)(p & 0xffffffffll) * (1.0f / 4294967296.0f);
+  return (hi < 0) ? 0.f : ((hi > n - 2) ? 1.f : fr);
 }
 
 template <typename T>
@@ -124,23 +128,59 @@ struct Gather {
   float fx, fy, fz;
 };
 
-// Gather the 8 voxels around a sample point.  WIDE: the brick's blocked array is
-// 4 GiB or more, so offsets are formed in 64 bits; otherwise as 32-bit byte
-// offsets from the brick base.
+// The loaded voxels of a sample's 8-voxel footprint, before decoding (FP16: the
+// four voxel pairs as loaded), so a request in flight holds as few registers as
+// possible.
+template <typename T>
+struct Voxels;
+template <>
+struct Voxels<float> {
+  float v[8];
+};
+template <>
+struct Voxels<__half> {
+  uint32_t c[4];
+};
+
+// Load the 8 voxels around a sample point.  Byte offsets from the brick base:
+// 32-bit sums of per-axis terms for bricks below 4 GiB; WIDE (the blocked array is
+// 4 GiB or more, or 64-bit offsets were asked for): 32-bit element indices (a
+// brick holds fewer than 2^32 elements), widened and scaled once per load.
+// Either way the loads are global loads.  An FP16 brick is stored as voxel pairs
+// when addressed with 32-bit offsets and as 2-byte voxels when addressed with
+// 64-bit offsets (the commit picks the layout and the addressing together).
 template <typename T, bool WIDE>
-__device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const int64_t p[3], Gather<T>& g) {
-  int lx, ly, lz;
-  clamp_axis(p[0], sc.dims[0], b.slo[0], b.sdim[0], lx, g.fx);
-  clamp_axis(p[1], sc.dims[1], b.slo[1], b.sdim[1], ly, g.fy);
-  clamp_axis(p[2], sc.dims[2], b.slo[2], b.sdim[2], lz, g.fz);
-  if constexpr (WIDE && sizeof(T) == 2) {
-    // FP16 elements hold voxel pairs (x, x + 1)
-    const uint32_t* pv = (const uint32_t*)b.data;
-    const uint32_t x0 = blk_x(lx);
-    const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
-    const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
-    const float2 c0 = unpack_pair_f16(pv[x0 + y0 + z0]), c1 = unpack_pair_f16(pv[x0 + y1 + z0]);
-    const float2 c2 = unpack_pair_f16(pv[x0 + y0 + z1]), c3 = unpack_pair_f16(pv[x0 + y1 + z1]);
+__device__ __forceinline__ void load_voxels(const SceneG& sc, const BrickG& b, const int64_t p[3], Voxels<T>& g) {
+  const int lx = axis_index(p[0], sc.dims[0], b.slo[0], b.sdim[0]);
+  const int ly = axis_index(p[1], sc.dims[1], b.slo[1], b.sdim[1]);
+  const int lz = axis_index(p[2], sc.dims[2], b.slo[2], b.sdim[2]);
+  using GC = const char __attribute__((address_space(1)))*;
+  if constexpr (sizeof(T) == 4) {
+    constexpr int SH = 2;
+    uint32_t x0, x1, y0, y1, z0, z1;
+    if constexpr (WIDE) {
+      x0 = blk_x(lx), x1 = blk_x(lx + 1);
+      y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
+      z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
+    } else {
+      const uint32_t bsy = b.bsy << SH, bsz = b.bsz << SH;
+      x0 = blkb_x<SH>(lx), x1 = blkb_x<SH>(lx + 1);
+      y0 = blkb_y<SH>(ly, bsy), y1 = blkb_y<SH>(ly + 1, bsy);
+      z0 = blkb_z<SH>(lz, bsz), z1 = blkb_z<SH>(lz + 1, bsz);
+    }
+    // byte offset of the element at the sum of the per-axis terms
+    auto off = [](uint32_t e) {
+      if constexpr (WIDE)
+        return (uint64_t)e << SH;
+      else
+        return e;
+    };
+    const uint32_t a00 = x0 + y0, a01 = x0 + y1;
+    // voxel lx + 1 follows voxel lx in memory unless lx ends a 4-voxel x-run, so
+    // each x-pair is one 8-byte load; lanes at a run's end read lx + 1 on their
+    // own.
+    const float2 c0 = load_pair_f32(b.data, off(a00 + z0)), c1 = load_pair_f32(b.data, off(a01 + z0));
+    const float2 c2 = load_pair_f32(b.data, off(a00 + z1)), c3 = load_pair_f32(b.data, off(a01 + z1));
     g.v[0] = c0.x;
     g.v[1] = c0.y;
     g.v[2] = c1.x;
@@ -149,64 +189,85 @@ __device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const 
     g.v[5] = c2.y;
     g.v[6] = c3.x;
     g.v[7] = c3.y;
+    if ((lx & 3) == 3) {
+      const uint32_t a10 = x1 + y0, a11 = x1 + y1;
+      g.v[1] = load_voxel_b<T>(b.data, off(a10 + z0));
+      g.v[3] = load_voxel_b<T>(b.data, off(a11 + z0));
+      g.v[5] = load_voxel_b<T>(b.data, off(a10 + z1));
+      g.v[7] = load_voxel_b<T>(b.data, off(a11 + z1));
+    }
   } else if constexpr (WIDE) {
-    const T* vox = (const T*)b.data;
-    const uint32_t x0 = blk_x(lx), x1 = blk_x(lx + 1);
+    // FP16 voxels (2 bytes: the layout of bricks addressed with 64-bit offsets):
+    // the aligned 4-voxel run holding lx is one 8-byte load and the pair
+    // (lx, lx + 1) is shifted out of it; lanes whose lx ends a run read lx + 1 on
+    // their own.  Element offsets are 32-bit sums (a brick holds fewer than 2^32
+    // elements), widened and scaled once per load.
+    using GU64 = const uint64_t __attribute__((address_space(1)))*;
+    using GU16 = const uint16_t __attribute__((address_space(1)))*;
     const uint32_t y0 = blk_y(ly, b.bsy), y1 = blk_y(ly + 1, b.bsy);
     const uint32_t z0 = blk_z(lz, b.bsz), z1 = blk_z(lz + 1, b.bsz);
-    g.v[0] = load_voxel<T>(vox, x0 + y0 + z0);
-    g.v[1] = load_voxel<T>(vox, x1 + y0 + z0);
-    g.v[2] = load_voxel<T>(vox, x0 + y1 + z0);
-    g.v[3] = load_voxel<T>(vox, x1 + y1 + z0);
-    g.v[4] = load_voxel<T>(vox, x0 + y0 + z1);
-    g.v[5] = load_voxel<T>(vox, x1 + y0 + z1);
-    g.v[6] = load_voxel<T>(vox, x0 + y1 + z1);
-    g.v[7] = load_voxel<T>(vox, x1 + y1 + z1);
+    const uint32_t x0 = blk_x(lx & ~3);
+    auto off = [](uint32_t e) { return (uint64_t)e << 1; };
+    const uint32_t a00 = x0 + y0, a01 = x0 + y1;
+    const uint32_t rs = (uint32_t)(lx & 3) << 4;
+    g.c[0] = (uint32_t)(*(GU64)((GC)b.data + off(a00 + z0)) >> rs);
+    g.c[1] = (uint32_t)(*(GU64)((GC)b.data + off(a01 + z0)) >> rs);
+    g.c[2] = (uint32_t)(*(GU64)((GC)b.data + off(a00 + z1)) >> rs);
+    g.c[3] = (uint32_t)(*(GU64)((GC)b.data + off(a01 + z1)) >> rs);
+    if ((lx & 3) == 3) {
+      const uint32_t x1 = blk_x(lx + 1), a10 = x1 + y0, a11 = x1 + y1;
+      g.c[0] = (g.c[0] & 0xffffu) | ((uint32_t) * (GU16)((GC)b.data + off(a10 + z0)) << 16);
+      g.c[1] = (g.c[1] & 0xffffu) | ((uint32_t) * (GU16)((GC)b.data + off(a11 + z0)) << 16);
+      g.c[2] = (g.c[2] & 0xffffu) | ((uint32_t) * (GU16)((GC)b.data + off(a10 + z1)) << 16);
+      g.c[3] = (g.c[3] & 0xffffu) | ((uint32_t) * (GU16)((GC)b.data + off(a11 + z1)) << 16);
+    }
   } else {
-    constexpr int SH = 2;  // 4-byte elements: FP32 voxels or FP16 voxel pairs
+    // FP16 voxel pairs (4 bytes, the layout of bricks below 4 GiB): each element
+    // holds the voxels (x, x + 1), one aligned 4-byte load per pair
+    constexpr int SH = 2;
+    using GU = const uint32_t __attribute__((address_space(1)))*;
     const uint32_t bsy = b.bsy << SH, bsz = b.bsz << SH;
-    const uint32_t x0 = blkb_x<SH>(lx), x1 = blkb_x<SH>(lx + 1);
+    const uint32_t x0 = blkb_x<SH>(lx);
     const uint32_t y0 = blkb_y<SH>(ly, bsy), y1 = blkb_y<SH>(ly + 1, bsy);
     const uint32_t z0 = blkb_z<SH>(lz, bsz), z1 = blkb_z<SH>(lz + 1, bsz);
-    if constexpr (sizeof(T) == 4) {
-      // voxel lx + 1 follows voxel lx in memory unless lx ends a 4-voxel x-run, so
-      // each x-pair is one 8-byte load; lanes at a run's end read lx + 1 on their
-      // own.  F16 keeps one load per voxel: a 4-byte pair load at 2-byte alignment,
-      // and an aligned 8-byte run load shifted to the pair, both measured slower.
-      const uint32_t a00 = x0 + y0, a01 = x0 + y1;
-      const float2 c0 = load_pair_f32(b.data, a00 + z0), c1 = load_pair_f32(b.data, a01 + z0);
-      const float2 c2 = load_pair_f32(b.data, a00 + z1), c3 = load_pair_f32(b.data, a01 + z1);
-      g.v[0] = c0.x;
-      g.v[1] = c0.y;
-      g.v[2] = c1.x;
-      g.v[3] = c1.y;
-      g.v[4] = c2.x;
-      g.v[5] = c2.y;
-      g.v[6] = c3.x;
-      g.v[7] = c3.y;
-      if ((lx & 3) == 3) {
-        const uint32_t a10 = x1 + y0, a11 = x1 + y1;
-        g.v[1] = load_voxel_b<T>(b.data, a10 + z0);
-        g.v[3] = load_voxel_b<T>(b.data, a11 + z0);
-        g.v[5] = load_voxel_b<T>(b.data, a10 + z1);
-        g.v[7] = load_voxel_b<T>(b.data, a11 + z1);
-      }
-    } else {
-      // FP16: each element holds the voxel pair (x, x + 1), one aligned 4-byte load
-      (void)x1;
-      const uint32_t a00 = x0 + y0, a01 = x0 + y1;
-      const float2 c0 = load_pair_f16(b.data, a00 + z0), c1 = load_pair_f16(b.data, a01 + z0);
-      const float2 c2 = load_pair_f16(b.data, a00 + z1), c3 = load_pair_f16(b.data, a01 + z1);
-      g.v[0] = c0.x;
-      g.v[1] = c0.y;
-      g.v[2] = c1.x;
-      g.v[3] = c1.y;
-      g.v[4] = c2.x;
-      g.v[5] = c2.y;
-      g.v[6] = c3.x;
-      g.v[7] = c3.y;
+    const uint32_t a00 = x0 + y0, a01 = x0 + y1;
+    g.c[0] = *(GU)((GC)b.data + a00 + z0);
+    g.c[1] = *(GU)((GC)b.data + a01 + z0);
+    g.c[2] = *(GU)((GC)b.data + a00 + z1);
+    g.c[3] = *(GU)((GC)b.data + a01 + z1);
+  }
+}
+
+// The 8 footprint voxels as FP32: (x0, x1) at (y0, z0), (y1, z0), (y0, z1), (y1, z1).
+template <typename T>
+__device__ __forceinline__ void decode_voxels(const Voxels<T>& g, float v[8]) {
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = g.v[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float2 c = unpack_pair_f16(g.c[k]);
+      v[2 * k] = c.x;
+      v[2 * k + 1] = c.y;
     }
   }
+}
+
+// Trilinear fractions of a sample point.
+__device__ __forceinline__ void sample_frac(const SceneG& sc, const int64_t p[3], float& fx, float& fy, float& fz) {
+  fx = axis_frac(p[0], sc.dims[0]);
+  fy = axis_frac(p[1], sc.dims[1]);
+  fz = axis_frac(p[2], sc.dims[2]);
+}
+
+// Gather the 8 voxels around a sample point and its trilinear fractions.
+template <typename T, bool WIDE>
+__device__ __forceinline__ void gather(const SceneG& sc, const BrickG& b, const int64_t p[3], Gather<T>& g) {
+  sample_frac(sc, p, g.fx, g.fy, g.fz);
+  Voxels<T> raw;
+  load_voxels<T, WIDE>(sc, b, p, raw);
+  decode_voxels<T>(raw, g.v);
 }
 
 template <typename T>
@@ -321,6 +382,144 @@ __device__ __forceinline__ void iso_hit(const SceneG& sc, const BrickG& b, const
   tr = 0.f;
 }
 
+// Emission-absorption march (no iso-surface) with a deeper pipeline: the voxels
+// of the next two samples are in flight while a sample is shaded, and the
+// majorant of the next run's macrocell is requested at the start of a run, so a
+// lane waits on memory about once per sample rather than once per sample plus
+// once per run.  Three gather buffers rotate; a run of a multiple of three
+// samples leaves the two buffers after it holding the next run's first two
+// samples.  Same lattice points, the same skip decisions, the same shading
+// order and the same termination test as the single-lookahead loop, so the
+// same bits.
+constexpr int kPipeRun = 6;  // samples per run in a non-empty macrocell (a multiple of 3)
+
+template <typename T, bool SKIP, bool WIDE>
+__device__ __forceinline__ bool ray_advance_ea(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
+                                               const float4* __restrict__ tfs, RayState& r, int budget,
+                                               int min_lanes) {
+  const float Ddt = sc.density * sc.dt_f;
+  const int64_t half = 0x80000000ll;
+  int s = r.s;
+  int n = r.n;
+  int64_t p0 = r.p[0], p1 = r.p[1], p2 = r.p[2];
+  const int64_t d0 = r.dp[0], d1 = r.dp[1], d2 = r.dp[2];
+  float tr = r.T, cr = r.cr, cg = r.cg, cb = r.cb;
+  double tau_acc = r.tau;
+  bool done = false;
+  Voxels<T> ga, gb, gc;
+  bool pre = false;      // ga, gb hold the voxels of samples s and s + 1
+  int64_t q0 = 0, q1 = 0, q2 = 0;  // point of the next sample to request
+  float mj_next = 0.f;
+  bool have_mj = false;  // mj_next is the majorant of sample s's macrocell
+  auto macrocell = [&](int64_t x, int64_t y, int64_t z, int m[3]) {
+    const int64_t pp[3] = {x, y, z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int cell = (int)((pp[a] + half) >> 32);
+      m[a] = min(max((cell - b.olo[a]) >> b.mc_shift, 0), b.mdim[a] - 1);
+    }
+  };
+  auto majorant = [&](const int m[3]) { return ld_global(b.majorant, (m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]); };
+  auto request = [&](Voxels<T>& g) {
+    const int64_t q[3] = {q0, q1, q2};
+    load_voxels<T, WIDE>(sc, b, q, g);
+    q0 += d0;
+    q1 += d1;
+    q2 += d2;
+  };
+  // shade sample s from its voxels; its fractions come from its point, p
+  auto step = [&](const Voxels<T>& g) -> bool {
+    Gather<T> gg;
+    const int64_t pc[3] = {p0, p1, p2};
+    sample_frac(sc, pc, gg.fx, gg.fy, gg.fz);
+    decode_voxels<T>(g, gg.v);
+    const float Dl = (s == r.s0) ? r.dl_first : ((s == r.s1) ? r.dl_last : Ddt);
+    ++n;
+    ++s;
+    p0 += d0;
+    p1 += d1;
+    p2 += d2;
+    return shade<T>(sc, tfb, tfs, gg, Dl, tau_acc, tr, cr, cg, cb);
+  };
+  while (!done && s <= r.s1 && budget > 0) {
+    // at a run boundary: return early (unfinished) once fewer than min_lanes lanes
+    // of the wave are still marching, so the caller can refill the idle ones
+    if (__popcll(__ballot(1)) < min_lanes) break;
+    int run = min(r.s1 - s + 1, budget);
+    if constexpr (SKIP) {
+      int m[3];
+      macrocell(p0, p1, p2, m);
+      const float mj = have_mj ? mj_next : majorant(m);
+      if (mj == 0.f) {
+        // exactly the samples left inside this empty macrocell (outer cells
+        // unbounded); every one has opacity exactly 0
+        const int64_t pp[3] = {p0, p1, p2}, dd[3] = {d0, d1, d2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int ma = m[a];
+          const int64_t blo = (ma == 0) ? INT64_MIN
+                                        : ((int64_t)(b.olo[a] + (ma << b.mc_shift)) << 32) - half;
+          const int64_t bhi = (ma == b.mdim[a] - 1) ? INT64_MAX
+                                                    : ((int64_t)(b.olo[a] + ((ma + 1) << b.mc_shift)) << 32) - half;
+          run = min(run, 1 + steps_inside(pp[a], dd[a], blo, bhi, run - 1));
+        }
+        s += run;
+        n += run;
+        budget -= run;
+        p0 += (int64_t)run * d0;
+        p1 += (int64_t)run * d1;
+        p2 += (int64_t)run * d2;
+        pre = false;
+        have_mj = false;
+        continue;
+      }
+      // a non-empty macrocell: a fixed number of samples, then look again (the
+      // run may cross into other macrocells; a sample of zero opacity changes
+      // nothing, so its length needs no exact boundary arithmetic)
+      run = min(run, kPipeRun);
+      int mn[3];
+      macrocell(p0 + (int64_t)run * d0, p1 + (int64_t)run * d1, p2 + (int64_t)run * d2, mn);
+      mj_next = majorant(mn);
+      have_mj = true;
+    }
+    budget -= run;
+    if (!pre) {
+      q0 = p0;
+      q1 = p1;
+      q2 = p2;
+      request(ga);
+      request(gb);
+    }
+    // the request two samples ahead is unconditional (past the run's last sample
+    // it reads clamped, in-brick voxels that are never used).  Three buffers
+    // rotate by position (no register copies: copying a buffer whose load is in
+    // flight would wait for it), and the loop body has no exit: a step past the
+    // run's end or after termination is skipped, not left, which keeps the
+    // control flow simple enough for the buffers to stay in place
+    for (int i = 0; i < run; i += 3) {
+      request(gc);
+      if (!done) done = step(ga);
+      request(ga);
+      if (!done && i + 1 < run) done = step(gb);
+      request(gb);
+      if (!done && i + 2 < run) done = step(gc);
+    }
+    pre = !done && run % 3 == 0;
+  }
+  // the fixed-point position always corresponds to segment s
+  r.s = s;
+  r.p[0] = p0;
+  r.p[1] = p1;
+  r.p[2] = p2;
+  r.T = tr;
+  r.cr = cr;
+  r.cg = cg;
+  r.cb = cb;
+  r.tau = tau_acc;
+  r.n = n;
+  return done || s > r.s1;
+}
+
 // Advance by at most `budget` lattice segments.  Returns true once the ray is
 // finished: past its last segment, or terminated early (1 - T >= ert, tested
 // after every segment that changed T).
@@ -328,6 +527,7 @@ template <typename T, bool SKIP, bool WIDE, bool ISO>
 __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, const float4* __restrict__ tfb,
                                             const float4* __restrict__ tfs, RayState& r, int budget,
                                             int min_lanes = 0) {
+  if constexpr (!ISO) return ray_advance_ea<T, SKIP, WIDE>(sc, b, tfb, tfs, r, budget, min_lanes);
   const float Ddt = sc.density * sc.dt_f;
   int s = r.s;
   int n = r.n;
@@ -359,7 +559,7 @@ __device__ __forceinline__ bool ray_advance(const SceneG& sc, const BrickG& b, c
         const int cell = (int)((pp[a] + half) >> 32);
         m[a] = min(max((cell - b.olo[a]) >> b.mc_shift, 0), b.mdim[a] - 1);
       }
-      const float mj = b.majorant[(m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]];
+      const float mj = ld_global(b.majorant, (m[2] * b.mdim[1] + m[1]) * b.mdim[0] + m[0]);
       if constexpr (ISO) {
         empty = mj <= 0.f && (!(pst & kIsoPair) || ((mj < 0.f) == (bool)(pst & kIsoSide)));
         if (empty) pst = kIsoPair | (mj < 0.f ? kIsoSide : 0);

@@ -146,7 +146,11 @@ BrickG Brick::device_view(bool with_majorant, bool force_wide) const {
   g.bsy = (uint32_t)kBlockVoxels * (uint32_t)bdim[0];
   g.bsz = (uint32_t)kBlockVoxels * (uint32_t)bdim[0] * (uint32_t)bdim[1];
   g.majorant = with_majorant ? maj : nullptr;
-  g.wide = force_wide || (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * 4u > 0xffffffffull;
+  // an FP16 brick's addressing follows its layout (2-byte voxels: 64-bit offsets)
+  if (dtype == DPR_F16)
+    g.wide = half16 ? 1 : 0;
+  else
+    g.wide = force_wide || (uint64_t)bdim[0] * bdim[1] * bdim[2] * kBlockVoxels * 4u > 0xffffffffull;
   int sh = 0;
   while ((1 << sh) < mc) ++sh;
   g.mc_shift = sh;
@@ -433,7 +437,7 @@ dpr_status dpr_world_add_brick(dpr_world w, const void* voxels, dpr_dtype dtype,
                 (unsigned long long)blocked);
   b.dtype = dtype;
   size_t bytes = n * b.elem();
-  dpr_status st = dev_alloc(&b.linear, bytes, "brick voxels");
+  dpr_status st = dev_alloc(&b.linear, bytes + kLinearSlack, "brick voxels");
   if (st != DPR_OK) return st;
   hipError_t e = hipMemcpyAsync(b.linear, voxels, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                 w->dev->stream);
@@ -516,10 +520,24 @@ dpr_status dpr_world_commit(dpr_world w) {
   dpr_status st = check_partition(w);
   if (st != DPR_OK) return st;
   const int mc = w->params.macrocell_cells;
+  // FP16 layout, one for the whole world (the batched kernel reads every brick the
+  // same way): 2-byte voxels when asked for (or 64-bit offsets were), or when some
+  // brick's voxel-pair copy would reach 4 GiB; else voxel pairs
+  bool f16_halves = (w->params.flags & (DPR_FLAG_F16_HALVES | DPR_FLAG_WIDE_OFFSETS)) != 0;
+  for (const auto& b : w->bricks)
+    f16_halves |= b.dtype == DPR_F16 &&
+                  (uint64_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * 4u >= kF16HalvesFrom;
   for (auto& b : w->bricks) {
+    // a change of layout re-allocates the blocked copy
+    const bool half16 = b.dtype == DPR_F16 && f16_halves;
+    if (b.blocked && half16 != b.half16) {
+      DPR_HIP(hipStreamSynchronize(w->dev->stream));
+      dev_free(b.blocked);
+      b.blocked = nullptr;
+    }
+    b.half16 = half16;
     if (!b.blocked) {
-      // 4-byte elements: an FP32 voxel, or the FP16 voxel pair (x, x + 1)
-      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * 4u + kPairSlack;
+      size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.blocked_elem() + kPairSlack;
       st = dev_alloc(&b.blocked, bytes, "blocked brick");
       if (st != DPR_OK) return st;
       // padding voxels (beyond the stored dims) are never written by the commit
@@ -543,7 +561,7 @@ dpr_status dpr_world_commit(dpr_world w) {
     b.maj_tf_version = 0;
   }
   std::vector<McBrick> mcb;
-  for (auto& b : w->bricks) mcb.push_back({b.linear, b.device_view(false), b.ranges, b.dtype == DPR_F16});
+  for (auto& b : w->bricks) mcb.push_back({b.linear, b.device_view(false), b.ranges, b.dtype == DPR_F16, b.half16});
   DPR_HIP(launch_commit(mcb.data(), (int)mcb.size(), mc, w->dev->stream));
   // (stream-ordered: later renders on the device stream see the new data; the
   // host does not wait)
@@ -653,6 +671,8 @@ dpr_status dpr_set_render_params(dpr_world w, const dpr_render_params* p) {
     return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_render_params: macrocell_cells %d not a power of two in [2, 64]",
                 mc);
   if (mc != w->params.macrocell_cells) w->committed = false;
+  // the FP16 layout (and with it the FP16 addressing) is chosen at commit
+  if ((p->flags ^ w->params.flags) & (DPR_FLAG_F16_HALVES | DPR_FLAG_WIDE_OFFSETS)) w->committed = false;
   w->params = *p;
   return DPR_OK;
 }
@@ -771,6 +791,21 @@ dpr_status dpr_render_partial(dpr_world w, int32_t id, dpr_frame out) {
   st = ensure_majorants(w);
   if (st != DPR_OK) return st;
   return render_brick(w, id, out);
+}
+
+dpr_status dpr_measure_gather(dpr_world w, int32_t id, const int32_t* counts, float* sink) {
+  if (!w || !counts || !sink) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_measure_gather: NULL argument");
+  dpr_status st = check_renderable(w, "dpr_measure_gather");
+  if (st != DPR_OK) return st;
+  if (id < 0 || id >= (int)w->bricks.size())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_measure_gather: brick %d does not exist", id);
+  st = ensure_majorants(w);
+  if (st != DPR_OK) return st;
+  const Brick& b = w->bricks[id];
+  const bool skip = !(w->params.flags & DPR_FLAG_NO_SKIP);
+  DPR_HIP(launch_gather_probe(make_scene(w), b.device_view(skip, w->params.flags & DPR_FLAG_WIDE_OFFSETS),
+                              make_cam(w->cam), b.dtype == DPR_F16, counts, sink, w->dev->stream));
+  return DPR_OK;
 }
 
 dpr_status dpr_composite(dpr_device d, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out) {

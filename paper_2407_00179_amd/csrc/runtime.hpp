@@ -97,7 +97,10 @@ struct Brick {
   int mdim[3] = {0, 0, 0};
   int mc = 0;
   uint64_t maj_tf_version = 0;
+  bool half16 = false;        // FP16 blocked copy of 2-byte voxels (else 4-byte voxel pairs)
   size_t elem() const { return dtype == DPR_F16 ? 2 : 4; }
+  // bytes of one element of the blocked copy
+  size_t blocked_elem() const { return dtype == DPR_F16 && half16 ? 2 : 4; }
   BrickG device_view(bool with_majorant, bool force_wide = false) const;
 };
 

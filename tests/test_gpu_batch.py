@@ -64,28 +64,33 @@ def test_batch_equals_render_frame_bitwise(gpu_lib, dpr, dtype, ert):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float16])
-def test_wide_offsets_bitwise(gpu_lib, dpr, dtype):
+def test_wide_offsets_and_f16_layouts_bitwise(gpu_lib, dpr, dtype):
     """Voxel offsets formed in 64 bits (the path of bricks of 4 GiB or more, forced
-    here on small bricks) give the same bits as 32-bit byte offsets, per brick and
-    batched."""
+    here on small bricks) and FP16 bricks stored as 2-byte voxels instead of voxel
+    pairs (automatic from 4 GiB pair copies, forced here) give the same bits as
+    32-bit offsets into voxel pairs, per brick and batched."""
     dims, vol, boxes, tf = _scene(dtype)
     prm = RenderParams(0.5, 0.99, 25.0)
     cams = _cams(dims)
     w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
     frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
     res = []
-    for flags in (0, dpr.FLAG_WIDE_OFFSETS):
+    variants = (0, dpr.FLAG_WIDE_OFFSETS, dpr.FLAG_F16_HALVES, dpr.FLAG_F16_HALVES | dpr.FLAG_WIDE_OFFSETS)
+    for flags in variants:
         w.set_params(dpr.Params(prm.step_voxels, prm.ert, 8, flags))
+        w.commit()
         w.render_batch(cams, frames)
         batch = [frame_np(f)[:2] for f in frames]
         w.render_batch(cams, frames, dpr.FLAG_PLAIN)
         plain = [frame_np(f)[:2] for f in frames]
         res.append((batch, plain))
-    for (b0, p0), (b1, p1) in [(res[0], res[1])]:
+    b0, p0 = res[0]
+    for v, (b1, p1) in zip(variants[1:], res[1:]):
         for c in range(len(cams)):
-            assert np.array_equal(b0[c][0], b1[c][0]) and np.array_equal(b0[c][1], b1[c][1]), c
-            assert np.array_equal(p0[c][0], p1[c][0]) and np.array_equal(p0[c][1], p1[c][1]), c
-            assert np.array_equal(b0[c][0], p0[c][0]), c
+            assert np.array_equal(b0[c][0], b1[c][0]) and np.array_equal(b0[c][1], b1[c][1]), (v, c)
+            assert np.array_equal(p0[c][0], p1[c][0]) and np.array_equal(p0[c][1], p1[c][1]), (v, c)
+    for c in range(len(cams)):
+        assert np.array_equal(b0[c][0], p0[c][0]), c
     w.release()
 
 

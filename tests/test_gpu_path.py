@@ -116,14 +116,14 @@ def test_bricking_does_not_change_a_bit(gpu_lib, dpr):
         assert st["forwards"] > outs[0][1]["forwards"]
 
 
-def test_wide_offsets_give_the_same_bits(gpu_lib, dpr):
+def test_wide_offsets_and_f16_layouts_give_the_same_bits(gpu_lib, dpr):
     dims = (40, 36, 32)
     vol = _volume(dims, 51, np.float16)
     tf = _tf(3005)
     prm = RenderParams(0.5, 1.0, 20.0)
     cam = orbit_camera(dims, 40, 32, dist=1.7)
     outs = []
-    for flags in (0, dpr.FLAG_WIDE_OFFSETS):
+    for flags in (0, dpr.FLAG_WIDE_OFFSETS, dpr.FLAG_F16_HALVES):
         w = make_world(dpr, gpu_lib, vol, dims, kd_split(dims, 5, seed=2, max_ratio=3.0), tf, prm, cam, mc=8,
                        flags=flags)
         f = dpr.Frame(gpu_lib, cam.width, cam.height)
@@ -131,7 +131,8 @@ def test_wide_offsets_give_the_same_bits(gpu_lib, dpr):
         outs.append((frame_np(f)[0], st))
         f.release()
         w.release()
-    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and outs[0][1] == o[1]
 
 
 def test_repeatable_and_seeded(gpu_lib, dpr):

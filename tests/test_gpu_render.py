@@ -120,15 +120,15 @@ def test_bricks_partials_and_frame(gpu_lib, dpr, split, ert):
     w.release()
 
 
-@pytest.mark.parametrize("dtype", [np.float32, np.float16])
-def test_skip_is_bitwise_neutral(gpu_lib, dpr, dtype):
+@pytest.mark.parametrize("dtype,base", [(np.float32, 0), (np.float16, 0), (np.float16, 0x10)])
+def test_skip_is_bitwise_neutral(gpu_lib, dpr, dtype, base):
     dims = (64, 56, 48)
     vol, tf = _small_case(dims, seed=21, nb=4, dtype=dtype)
     prm = RenderParams(0.5, 0.99, 20.0)
     cam = orbit_camera(dims, 96, 80)
     boxes = even_split(dims, (2, 1, 2))
     res = []
-    for flags in (0, 1):
+    for flags in (base, base | 1):
         w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, flags=flags)
         out = dpr.Frame(gpu_lib, cam.width, cam.height, counts=True)
         w.render_partial(1, out)
@@ -244,13 +244,16 @@ def test_macrocells_wide_bricks(gpu_lib, dpr, dims, dtype):
             w.release()
 
 
-def test_f16_volume(gpu_lib, dpr):
+@pytest.mark.parametrize("halves", [False, True])
+def test_f16_volume(gpu_lib, dpr, halves):
+    """FP16 bricks stored as voxel pairs and as 2-byte voxels."""
     dims = (50, 42, 36)
     vol, tf = _small_case(dims, seed=41, dtype=np.float16)
     prm = RenderParams(0.5, 0.99, 20.0)
     cam = orbit_camera(dims, 64, 64)
     boxes = even_split(dims, (2, 2, 1))
-    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, on_device=True)
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, on_device=True,
+                   flags=dpr.FLAG_F16_HALVES if halves else 0)
     py, px = np.mgrid[0:64, 0:64]
     px, py = px.ravel(), py.ravel()
     for i, (lo, hi) in enumerate(boxes):
