@@ -135,13 +135,17 @@ def bench_rank_share(args, dpr, torch, dev, keep_host):
     w.commit()
     w.set_transfer_function(tf, 0.0, 1.0, cfg.density)
     w.set_camera(cam)
-    # logical samples (counted by the plain march) and the plain per-brick march itself
+    # logical samples (per-pixel counts, written by the plain march) and the plain
+    # per-brick launch itself
     cf = dpr.Frame(dev, W, H, counts=True)
     w.render_partial(0, cf)
     dev.sync()
     samples = int(cf.counts.sum().item())
     hits = int(torch.isfinite(cf.depth).sum().item())
-    ms_plain = _timed(torch, lambda: w.render_partial(0, cf), 3)
+    pf = dpr.Frame(dev, W, H)
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_PLAIN))
+    ms_plain = _timed(torch, lambda: w.render_partial(0, pf), 3)
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH))
     # gather ceiling: the march's loads for the same samples, no dependence between samples
     sink = torch.empty((H, W), dtype=torch.float32, device=dev.torch_device)
     w.measure_gather(0, cf.counts, sink)
@@ -210,7 +214,7 @@ def bench_rank_share(args, dpr, torch, dev, keep_host):
         r0, r1 = H // 2 - 32, H // 2 + 32
         band = dict(rgba=rgba[:, r0:r1].cpu().numpy(), depth=depth[:, r0:r1].cpu().numpy(), ids=np.array(ids),
                     rows=(r0, r1))
-    for f in frames + [out, cf]:
+    for f in frames + [out, cf, pf]:
         f.release()
     w.release()
     del rgba, depth, sink
@@ -262,7 +266,11 @@ def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam):
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
     parts = [dpr.Frame(dev, W, H) for _ in range(K)]
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_PLAIN))
     ms_plain_march = _timed(torch, lambda: [w.render_partial(i, f) for i, f in enumerate(parts)], max(3, args.steps))
+    w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH))
+    # the same 8 partial frames through the persistent kernel, one brick per launch
+    ms_partials = _timed(torch, lambda: [w.render_partial(i, f) for i, f in enumerate(parts)], max(3, args.steps))
     live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
     comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
     ms_comp8 = _timed(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), max(3, args.steps))
@@ -276,6 +284,7 @@ def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam):
                 ms_batch_march=march, msamples_march=total / march / 1e3,
                 valu_frac=OPS_PER_SAMPLE * total / (march / 1e3) / 1e12 / VALU_PEAK_TOPS,
                 ms_plain_8_marches=ms_plain_march, batched_speedup_march=ms_plain_march / march,
+                ms_8_partials_persistent=ms_partials,
                 composite_k8=dict(ms=ms_comp8, algorithmic_bytes=comp_bytes, GBps=comp_bytes / ms_comp8 / 1e6,
                                   frac_hbm=comp_bytes / ms_comp8 / 1e6 / HBM_PEAK_GBS))
 

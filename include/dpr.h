@@ -221,7 +221,11 @@ void dpr_frame_release(dpr_frame);
  *   Output (C, 1 - T) at depth t_in; a miss writes (0,0,0,0) at +inf.
  * Segments whose sample point lies in a macrocell of majorant 0 are skipped;
  * they contribute exactly nothing, so skipping never changes a result.
- * The frame must match the camera's size.                                       */
+ * The frame must match the camera's size.  The brick's screen tiles go through
+ * the persistent kernel of dpr_render_batch (graph-replayed unless
+ * DPR_FLAG_NO_GRAPH); with DPR_FLAG_PLAIN in the render parameters, or with a
+ * sample-count buffer attached to `out` (dpr_frame_attach_counts), one plain
+ * launch of one thread per pixel renders it instead.  Both give the same bits. */
 dpr_status dpr_render_partial(dpr_world, int32_t brick_id, dpr_frame out);
 
 /* Sort-last composite (section 2.1; section 5.1.1): for each pixel, the k
@@ -272,10 +276,11 @@ dpr_status dpr_autotune_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_
 /* Force a tile shape (tile_w * tile_h must be a multiple of 64, <= 1024).      */
 dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
 /* Durations of the march kernel and of the tile compositor of the last batched
- * render (dpr_render_batch with DPR_FLAG_NO_GRAPH, or dpr_render_frame with
- * DPR_FLAG_NO_GRAPH in the render parameters), from HIP events recorded on the
- * device stream around each kernel.  Synchronises.  DPR_ERR_INVALID_STATE when
- * the last batched render was a graph replay (or there was none).             */
+ * render (dpr_render_batch with DPR_FLAG_NO_GRAPH, or dpr_render_frame or
+ * dpr_render_partial with DPR_FLAG_NO_GRAPH in the render parameters), from HIP
+ * events recorded on the device stream around each kernel.  Synchronises.
+ * DPR_ERR_INVALID_STATE when the last batched render was a graph replay (or
+ * there was none).                                                              */
 dpr_status dpr_batch_timings(dpr_world, float* march_ms, float* composite_ms);
 
 /* ---------------------------------------------------------------- measurement */

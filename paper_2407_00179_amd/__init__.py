@@ -330,6 +330,16 @@ def composite_noalloc(dev: Device, parts, out: Frame, ids=None):
 
 
 # ---------------------------------------------------------------- differentiable render
+def _follow_current_stream(dev, device):
+    """Point the library's device at torch's current stream (where the call's
+    buffers were just allocated and filled) and return that stream."""
+    torch = _torch()
+    stream = torch.cuda.current_stream(device)
+    if dev.stream is None or dev.stream.cuda_stream != stream.cuda_stream:
+        dev.set_stream(stream)
+    return stream
+
+
 def _cam_array(cams):
     return (N.Camera * len(cams))(*[to_c_camera(c) for c in cams])
 
@@ -355,6 +365,8 @@ def _make_fn():
         @staticmethod
         def forward(ctx, volume, tf, dev, cams, params, lo, hi, density):
             dims = _train_args(volume, tf)
+            # the library enqueues on the stream torch allocates and zero-fills on
+            _follow_current_stream(dev, volume.device)
             ca = _cam_array(cams)
             n, W, H = len(cams), int(cams[0].width), int(cams[0].height)
             nbytes = C.c_size_t()
@@ -376,6 +388,9 @@ def _make_fn():
         def backward(ctx, g_out, g_depth):
             volume, tf = ctx.saved_tensors
             dims = _train_args(volume, tf)
+            stream = _follow_current_stream(ctx.dev, volume.device)
+            # the forward's workspace is read here, possibly on another stream
+            ctx.ws.record_stream(stream)
             ca = _cam_array(ctx.cams)
             g = g_out.contiguous()
             gv = torch.zeros_like(volume)

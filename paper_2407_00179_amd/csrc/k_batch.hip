@@ -239,6 +239,7 @@ struct BatchState {
   std::vector<dpr_frame> outs;
   std::vector<const void*> out_ptrs;
   int tile_w = 0, tile_h = 0;
+  int brick_sel = -1;  // the one brick rendered (dpr_render_partial), or -1 for all
   uint64_t geo_version = 0;
   bool skip = true;
   // deep-frame target (dpr_render_deep) instead of flat frames, and its buffers
@@ -289,7 +290,9 @@ struct BatchState {
     head = nullptr;
     drop_graph();
   }
+  // 64-bit offsets for every brick if any brick the launch reads needs them
   bool wide() const {
+    if (brick_sel >= 0) return brick_sel < (int)h_bricks.size() && h_bricks[brick_sel].wide;
     for (const auto& g : h_bricks)
       if (g.wide) return true;
     return false;
@@ -399,7 +402,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool
   g.frag_rgba = b->frag_rgba;
   g.frag_depth = b->frag_depth;
   g.head = b->head;
-  const bool f16 = w->bricks[0].dtype == DPR_F16;
+  const bool f16 = w->bricks[b->brick_sel >= 0 ? b->brick_sel : 0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, b->head);
   if (timed) (void)hipEventRecord(b->ev[0], st);
@@ -441,7 +444,7 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool
 
 // (Re)build the item queue, tile lists and fragment storage for these cameras.
 static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams, int n, const dpr_frame* outs,
-                              int tw, int th) {
+                              int tw, int th, int brick_sel) {
   hipStream_t st = w->dev->stream;
   DPR_HIP(hipStreamSynchronize(st));
   b->free_device();
@@ -454,6 +457,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   }
   b->tile_w = tw;
   b->tile_h = th;
+  b->brick_sel = brick_sel;
   b->geo_version = w->geo_version;
   b->skip = !(w->params.flags & DPR_FLAG_NO_SKIP);
   const SceneG sc = make_scene(w);
@@ -475,6 +479,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   std::vector<std::vector<int>> per_tile(tile_base[n]);
   for (int c = 0; c < n; ++c) {
     for (int k = 0; k < (int)w->bricks.size(); ++k) {
+      if (brick_sel >= 0 && k != brick_sel) continue;
       const Brick& br = w->bricks[k];
       double lo[3], hi[3];
       for (int a = 0; a < 3; ++a) {
@@ -540,7 +545,7 @@ static dpr_status build_batch(dpr_world w, BatchState* b, const dpr_camera* cams
   for (auto& e : b->ev)
     if (!e) DPR_HIP(hipEventCreate(&e));
   // persistent grid: as many 256-thread workgroups as fit on the GPU at once
-  const bool f16 = w->bricks[0].dtype == DPR_F16;
+  const bool f16 = w->bricks[brick_sel >= 0 ? brick_sel : 0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   for (int iso = 0; iso < 2; ++iso) {
     int per_cu = 0;
@@ -604,8 +609,8 @@ static void deep_key(dpr_deep_frame d, const void* ptrs[4]) {
 }
 
 static bool same_key(const BatchState* b, dpr_world w, const dpr_camera* cams, int n, const dpr_frame* outs, int tw,
-                     int th, dpr_deep_frame deep, int rank) {
-  if (!b || b->tile_w != tw || b->tile_h != th || (int)b->cams.size() != n) return false;
+                     int th, dpr_deep_frame deep, int rank, int brick_sel) {
+  if (!b || b->tile_w != tw || b->tile_h != th || (int)b->cams.size() != n || b->brick_sel != brick_sel) return false;
   const void* dp[4];
   deep_key(deep, dp);
   if (b->deep != deep || b->deep_rank != rank || memcmp(b->deep_ptrs, dp, sizeof(dp)) != 0) return false;
@@ -675,14 +680,12 @@ static dpr_status render_plain(dpr_world w, const dpr_camera* cams, int n, dpr_f
   return DPR_OK;
 }
 
-static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n, dpr_frame* outs, uint32_t flags,
-                                     int tw, int th, dpr_deep_frame deep = nullptr, int rank = -1) {
-  if (!w->batch) w->batch = new BatchState;
-  BatchState* b = w->batch;
+static dpr_status render_batch_state(dpr_world w, BatchState* b, const dpr_camera* cams, int n, dpr_frame* outs,
+                                     uint32_t flags, int tw, int th, dpr_deep_frame deep, int rank, int brick_sel) {
   dpr_status s = ensure_majorants(w);
   if (s != DPR_OK) return s;
-  if (!same_key(b, w, cams, n, outs, tw, th, deep, rank)) {
-    s = build_batch(w, b, cams, n, outs, tw, th);
+  if (!same_key(b, w, cams, n, outs, tw, th, deep, rank, brick_sel)) {
+    s = build_batch(w, b, cams, n, outs, tw, th, brick_sel);
     if (s != DPR_OK) return s;
     b->deep = deep;
     b->deep_rank = rank;
@@ -691,6 +694,7 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
     s = refresh_batch(w, b);
     if (s != DPR_OK) return s;
   }
+  w->last_batch = b;
   if (flags & DPR_FLAG_NO_GRAPH) {
     DPR_HIP(enqueue_batch(w, b, w->dev->stream, true));
     b->timed = true;
@@ -703,6 +707,22 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
   DPR_HIP(hipGraphLaunch(b->exec, w->dev->stream));
   b->timed = false;
   return DPR_OK;
+}
+
+static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n, dpr_frame* outs, uint32_t flags,
+                                     int tw, int th, dpr_deep_frame deep = nullptr, int rank = -1) {
+  if (!w->batch) w->batch = new BatchState;
+  return render_batch_state(w, w->batch, cams, n, outs, flags, tw, th, deep, rank, -1);
+}
+
+// One brick's partial frame through the persistent kernel: items of that brick
+// only (one cached state per brick), every camera tile written by the tile pass
+// (tiles the brick does not cover come out empty).
+dpr_status render_partial_batched(dpr_world w, int id, dpr_frame out) {
+  if ((int)w->partial_batch.size() < (int)w->bricks.size()) w->partial_batch.resize(w->bricks.size(), nullptr);
+  if (!w->partial_batch[id]) w->partial_batch[id] = new BatchState;
+  return render_batch_state(w, w->partial_batch[id], &w->cam, 1, &out, w->params.flags & DPR_FLAG_NO_GRAPH,
+                            w->batch_tile_w, w->batch_tile_h, nullptr, -1, id);
 }
 
 dpr_status render_frame_batched(dpr_world w, dpr_frame out) {
@@ -756,7 +776,7 @@ dpr_status dpr_render_deep(dpr_world w, int32_t rank, dpr_deep_frame out) {
 
 dpr_status dpr_batch_timings(dpr_world w, float* march_ms, float* composite_ms) {
   if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_batch_timings: NULL world");
-  BatchState* b = w->batch;
+  BatchState* b = w->last_batch;
   if (!b || !b->timed || !b->ev[0])
     return fail(DPR_ERR_INVALID_STATE, "dpr_batch_timings: the last batched render was not enqueued directly");
   DPR_HIP(hipEventSynchronize(b->ev[2]));

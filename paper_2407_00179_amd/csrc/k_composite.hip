@@ -347,12 +347,14 @@ __global__ __launch_bounds__(256) void deep_merge_kernel(const CompTable* __rest
                                                          float* __restrict__ out_depth) {
   __shared__ const float* pdepth[kMaxFrags];
   __shared__ const int* pcount[kMaxFrags];
+  __shared__ int pcap[kMaxFrags];
   __shared__ int pkey[kMaxFrags];                  // rank-order index << 8
   __shared__ const float4* rgba_by_rank[kMaxFrags];
   for (int r = threadIdx.x; r < R; r += blockDim.x) {
     const int q = tab->idrank[r];
     pdepth[r] = tab->depth[r];
     pcount[r] = tab->count[r];
+    pcap[r] = tab->cap[r];
     pkey[r] = q << 8;
     rgba_by_rank[q] = tab->rgba[r];
   }
@@ -377,15 +379,19 @@ __global__ __launch_bounds__(256) void deep_merge_kernel(const CompTable* __rest
     for (int r0 = 0; r0 < R; r0 += 8) {
       int c[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) c[u] = r0 + u < R ? pcount[r0 + u][p] : 0;
+      // a count is trusted only up to the part's capacity (layers beyond it do not
+      // exist), and a fragment whose depth is not below +inf (NaN included) is not
+      // live, as in the flat compositor
+      for (int u = 0; u < 8; ++u) c[u] = r0 + u < R ? min(max(pcount[r0 + u][p], 0), pcap[r0 + u]) : 0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        n += c[u];
         if (c[u] <= 0) continue;
         const float* dz = pdepth[r0 + u] + p;
         const int kb = pkey[r0 + u];
         for (int l = 0; l < c[u]; ++l) {
           const float d = dz[(size_t)l * sP];
+          if (!(d < INFINITY)) continue;
+          ++n;
           const int key = kb | l;
           if (!key_less(lz, lk, d, key)) continue;                             // composited already
           if (m == kSel && !key_less(d, key, z[kSel - 1], kk[kSel - 1])) continue;  // beyond this pass
@@ -405,7 +411,8 @@ __global__ __launch_bounds__(256) void deep_merge_kernel(const CompTable* __rest
         }
       }
     }
-    if (done == 0 && m > 0) znear = z[0];
+    if (m == 0) break;  // nothing left beyond the last key (every pass selects at least one otherwise)
+    if (done == 0) znear = z[0];
 #pragma unroll
     for (int j = 0; j < kSel; ++j) {
       if (j < m) {

@@ -49,8 +49,10 @@ struct CompTable {
   const float4* rgba[kMaxFrags];
   const float* depth[kMaxFrags];
   int idrank[kMaxFrags];
-  // deep frames: per-pixel fragment counts of part k (null for flat frames)
+  // deep frames: per-pixel fragment counts of part k (null for flat frames) and
+  // its layer capacity (counts are clamped to it)
   const int* count[kMaxFrags];
+  int cap[kMaxFrags];
 };
 // fix_count / fix_list: device scratch for pixels whose fragments break the tile
 // order (fix_count: two ints, zero on entry and left zero on exit; fix_list holds

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(64) void table_fill_kernel(TableChunk c, CompTable*
     tab->depth[c.k0 + i] = c.depth[i];
     tab->idrank[c.k0 + i] = c.idrank[i];
     tab->count[c.k0 + i] = nullptr;
+    tab->cap[c.k0 + i] = 0;
   }
   // the fix-up counters must start at zero (the fix-up pass also leaves them so)
   if (c.k0 == 0 && i < 2) fix_count[i] = 0;

@@ -187,7 +187,8 @@ dpr_status ensure_majorants(dpr_world_t* w) {
 // Composite tables are cached per (frames, ids) so repeated composites of the same
 // frames (every dpr_render_frame) issue no host-to-device traffic at all.
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
-                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts) {
+                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts,
+                      const std::vector<int32_t>* caps) {
   const size_t k = rgba.size();
   std::vector<uint64_t> key;
   key.reserve(4 * k);
@@ -196,6 +197,7 @@ dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, co
     key.push_back((uint64_t)(uintptr_t)depth[i]);
     key.push_back((uint64_t)(uint32_t)ids[i]);
     key.push_back(counts ? (uint64_t)(uintptr_t)(*counts)[i] : 0);
+    key.push_back(caps ? (uint64_t)(uint32_t)(*caps)[i] : 0);
   }
   auto it = dev->comp_cache.find(key);
   if (it != dev->comp_cache.end()) {
@@ -223,6 +225,7 @@ dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, co
     e.host->rgba[i] = rgba[i];
     e.host->depth[i] = depth[i];
     e.host->count[i] = counts ? (*counts)[i] : nullptr;
+    e.host->cap[i] = caps ? (*caps)[i] : 0;
   }
   dpr_status st = dev_alloc((void**)&e.dev, sizeof(CompTable), "composite table");
   if (st != DPR_OK) {
@@ -397,6 +400,8 @@ void dpr_world_release(dpr_world w) {
   }
   for (auto f : w->partials) dpr_frame_release(f);
   if (w->batch) batch_state_free(w->batch);
+  for (auto b : w->partial_batch)
+    if (b) batch_state_free(b);
   if (w->path) path_state_free(w->path);
   dev_free(w->tf_dev);
   if (w->tf_host) (void)hipHostFree(w->tf_host);
@@ -790,6 +795,9 @@ dpr_status dpr_render_partial(dpr_world w, int32_t id, dpr_frame out) {
   if (out->dev != w->dev) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_render_partial: frame of another device");
   st = ensure_majorants(w);
   if (st != DPR_OK) return st;
+  // the persistent kernel, unless the plain launch is asked for or per-pixel
+  // sample counts are (only the plain launch writes them)
+  if (!(w->params.flags & DPR_FLAG_PLAIN) && !out->counts) return render_partial_batched(w, id, out);
   return render_brick(w, id, out);
 }
 
@@ -887,6 +895,7 @@ dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32
   std::vector<const float*> dp;
   std::vector<int32_t> ranks;
   std::vector<const int*> cnt;
+  std::vector<int32_t> caps;
   for (int j = 0; j < k; ++j) {
     const dpr_deep_frame f = parts[j];
     if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: part %d is NULL", j);
@@ -901,6 +910,7 @@ dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32
     dp.push_back(f->depth);
     ranks.push_back(f->rank);
     cnt.push_back(f->counts);
+    caps.push_back(f->cap);
   }
   // Ties in depth order as the fragments' ids: inside a part the layers are in
   // (depth, id) order, and ids of different parts differ in their rank, so the
@@ -910,7 +920,7 @@ dpr_status dpr_composite_deep(dpr_device dev, const dpr_deep_frame* parts, int32
   if (std::adjacent_find(sr.begin(), sr.end()) != sr.end())
     return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_composite_deep: the parts must come from distinct ranks");
   CompTable* tab = nullptr;
-  dpr_status st = comp_table(dev, rg, dp, ranks, &tab, &cnt);
+  dpr_status st = comp_table(dev, rg, dp, ranks, &tab, &cnt, &caps);
   if (st != DPR_OK) return st;
   DPR_HIP(launch_composite_deep(tab, k, (int)((size_t)out->w * out->h), (float4*)out->rgba, out->depth,
                                 dev->stream));

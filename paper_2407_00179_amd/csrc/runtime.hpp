@@ -132,6 +132,9 @@ struct dpr_world_t {
   // partial frames of dpr_render_frame (one per brick)
   std::vector<dpr_frame> partials;
   dpr::BatchState* batch = nullptr;
+  // per brick: the state of its partial renders through the persistent kernel
+  std::vector<dpr::BatchState*> partial_batch;
+  dpr::BatchState* last_batch = nullptr;  // the state of the last batched render
   dpr::PathState* path = nullptr;
   uint64_t geo_version = 1;  // bumped when a brick is added (invalidates batch item lists)
   uint64_t commit_version = 0;  // bumped by every commit (brick data may have changed)
@@ -149,6 +152,7 @@ SceneG make_scene(const dpr_world_t* w);
 dpr_status check_camera(const dpr_camera* c);
 dpr_status ensure_majorants(dpr_world_t* w);
 dpr_status render_frame_batched(dpr_world w, dpr_frame out);
+dpr_status render_partial_batched(dpr_world w, int id, dpr_frame out);
 dpr_status composite_frames(dpr_device dev, const dpr_frame* parts, const int32_t* ids, int32_t k, dpr_frame out);
 // Largest frame (pixels) dpr_composite_noalloc takes: its fix-up list is sized
 // for it (3840 x 2160 fits).
@@ -156,6 +160,7 @@ constexpr size_t kNoAllocMaxPixels = (size_t)1 << 23;
 // Look up this GPU's copy of the fixed scratch array (the device is current).
 dpr_status noalloc_setup(dpr_device d);
 dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, const std::vector<const float*>& depth,
-                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts = nullptr);
+                      const std::vector<int32_t>& ids, CompTable** out, const std::vector<const int*>* counts = nullptr,
+                      const std::vector<int32_t>* caps = nullptr);
 
 }  // namespace dpr

@@ -94,6 +94,39 @@ def test_wide_offsets_and_f16_layouts_bitwise(gpu_lib, dpr, dtype):
     w.release()
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("iso", [None, 0.45])
+def test_partial_through_persistent_kernel_equals_plain_launch(gpu_lib, dpr, dtype, iso):
+    """dpr_render_partial goes through the persistent kernel (one cached item list
+    per brick, graph-replayed or enqueued directly); the plain one-thread-per-pixel
+    launch (DPR_FLAG_PLAIN) gives the same bits for every brick, camera and tile
+    shape, including bricks off screen and a camera inside the volume."""
+    dims, vol, boxes, tf = _scene(dtype)
+    prm = RenderParams(0.5, 0.99, 25.0)
+    cams = _cams(dims)
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0], mc=8)
+    if iso is not None:
+        w.set_isosurface(iso)
+    for ci, c in enumerate(cams):
+        w.set_camera(c)
+        got = dpr.Frame(gpu_lib, c.width, c.height)
+        ref = dpr.Frame(gpu_lib, c.width, c.height)
+        for tile, flags in (((8, 8), 0), ((16, 16), dpr.FLAG_NO_GRAPH)):
+            w.set_batch_tile(*tile)
+            for i in range(len(boxes)):
+                got.rgba.fill_(-1.0)
+                got.depth.fill_(-1.0)
+                w.set_params(dpr.Params(prm.step_voxels, prm.ert, 8, flags))
+                w.render_partial(i, got)
+                w.set_params(dpr.Params(prm.step_voxels, prm.ert, 8, dpr.FLAG_PLAIN))
+                w.render_partial(i, ref)
+                g, r = frame_np(got)[:2], frame_np(ref)[:2]
+                assert np.array_equal(g[0], r[0]) and np.array_equal(g[1], r[1]), (ci, tile, i)
+        got.release()
+        ref.release()
+    w.release()
+
+
 def test_graph_replays_stay_exact(gpu_lib, dpr):
     import torch
     dims, vol, boxes, tf = _scene()

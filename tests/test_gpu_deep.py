@@ -175,6 +175,59 @@ def test_deep_composite_more_fragments_than_one_pass(gpu_lib, dpr):
         h.release()
 
 
+def test_deep_merge_ignores_bad_counts_and_depths(gpu_lib, dpr):
+    """Deep frames are writable by the caller: a count above the frame's capacity
+    is clamped to it, a negative count is 0, and a fragment whose depth is NaN or
+    +inf is not live (as in the flat compositor).  The merge then equals the
+    oracle's merge of the cleaned lists, and every pixel finishes."""
+    import torch
+    dims = (24, 20, 16)
+    vol = _volume(dims, 13)
+    tf = make_tf(2001)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    W, H, cap = 37, 23, 4
+    cam = orbit_camera(dims, W, H)
+    w = make_world(dpr, gpu_lib, vol, dims, even_split(dims, (2, 1, 1)), tf, prm, cam, mc=4)
+    rng = np.random.default_rng(99)
+    deeps, parts = [], []
+    P = W * H
+    for r in range(3):
+        d = dpr.DeepFrame(gpu_lib, W, H, cap)
+        w.render_deep(r, d)          # marks the frame as rank r's
+        cnt = rng.integers(-2, cap + 4, P)
+        z = rng.uniform(1.0, 2.0, (cap, P)).astype(np.float32)
+        z[rng.random((cap, P)) < 0.15] = np.nan
+        z[rng.random((cap, P)) < 0.10] = np.inf
+        a = rng.uniform(0.0, 0.8, (cap, P))
+        rgba = np.concatenate([rng.uniform(0, 1, (cap, P, 3)) * a[..., None], a[..., None]], -1).astype(np.float32)
+        d.counts.copy_(torch.from_numpy(cnt.astype(np.int32).reshape(H, W)))
+        d.depth.copy_(torch.from_numpy(z.reshape(cap, H, W)))
+        d.rgba.copy_(torch.from_numpy(rgba.reshape(cap, H, W, 4)))
+        # the cleaned list: live layers first, in layer order, ids rank-major
+        c2 = np.zeros(P, np.int64)
+        r2 = np.zeros((cap, P, 4))
+        z2 = np.full((cap, P), np.inf)
+        f2 = np.zeros((cap, P), np.int64)
+        for p in range(P):
+            for l in range(min(max(int(cnt[p]), 0), cap)):
+                if np.isfinite(z[l, p]):
+                    k = c2[p]
+                    r2[k, p], z2[k, p], f2[k, p] = rgba[l, p], z[l, p], r * 256 + l
+                    c2[p] += 1
+        parts.append((c2, r2, z2, f2))
+        deeps.append(d)
+    out = dpr.Frame(gpu_lib, W, H)
+    dpr.composite_deep(gpu_lib, deeps, out)
+    got, gz, _ = frame_np(out)
+    want, wz = oracle.composite_deep(parts)
+    err = np.max(np.abs(got - want))
+    log(f"deep merge with clamped counts and NaN/inf depths: max err {err:.3e}")
+    assert err <= TOL_F32
+    assert np.array_equal(gz, wz.astype(np.float32).astype(np.float64))
+    for h in deeps + [out, w]:
+        h.release()
+
+
 def test_deep_argument_errors(gpu_lib, dpr):
     dims = (24, 20, 16)
     vol = _volume(dims, 3)
