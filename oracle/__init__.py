@@ -48,7 +48,7 @@ ranges, finite differences and torch.autograd (FP64) for gradients.
 
 from .render import (  # noqa: F401
     RenderParams, camera_basis, camera_rays, clip_box, trilinear, tf_lookup,
-    march_rays, render_brick, render_image,
+    march_rays, march_rays_thresholds, render_brick, render_brick_thresholds, render_image,
 )
 from .composite import composite  # noqa: F401
 from .deep import FID_RANK, composite_deep, deep_frame  # noqa: F401

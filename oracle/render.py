@@ -196,6 +196,86 @@ def march_rays(data, stored_lo, dims, owned_lo, owned_hi, tf, params: RenderPara
     return rgba, depth, nsamp
 
 
+def march_rays_thresholds(data, stored_lo, dims, owned_lo, owned_hi, tf, params: RenderParams, o, d, thetas):
+    """The march of ``march_rays`` evaluated for several termination thresholds at
+    once (C10): one pass continues until the largest threshold stops a ray, and
+    each threshold keeps the accumulators as they stood after the segment at which
+    1 - T first reached it.  Returns a list of (rgba, depth, samples), one per
+    threshold; each equals ``march_rays`` with that threshold.
+    """
+    dims = tuple(int(v) for v in dims)
+    h = 1.0 / max(dims)
+    dt = params.step_voxels * h
+    D = params.density
+    thetas = [float(th) for th in thetas]
+    box_lo = np.array(owned_lo, dtype=np.float64) * h
+    box_hi = np.array(owned_hi, dtype=np.float64) * h
+    R = o.shape[0]
+    t_in, t_out, hit = clip_box(o, d, box_lo, box_hi)
+    C = np.zeros((R, 3))
+    T = np.ones(R)
+    nsamp = np.zeros(R, dtype=np.int64)
+    # per threshold: whether it has stopped the ray, and the state it stopped at
+    stopped = [np.zeros(R, dtype=bool) for _ in thetas]
+    keep = [(np.zeros((R, 3)), np.ones(R), np.zeros(R, dtype=np.int64)) for _ in thetas]
+    s0 = np.floor(t_in / dt)
+    s1 = np.ceil(t_out / dt) - 1.0
+    act = np.nonzero(hit)[0]
+    k = 0
+    while act.size:
+        s = s0[act] + k
+        seg_lo = np.maximum(s * dt, t_in[act])
+        seg_hi = np.minimum((s + 1.0) * dt, t_out[act])
+        ell = seg_hi - seg_lo
+        valid = ell > 0.0
+        tm = (s + 0.5) * dt
+        rgba = np.zeros((act.size, 4))
+        if valid.any():
+            p = o[act[valid]] + tm[valid, None] * d[act[valid]]
+            v = trilinear(data, stored_lo, dims, p / h - 0.5)
+            rgba[valid] = tf_lookup(tf, v, params.tf_lo, params.tf_hi)
+        tau = np.where(valid, D * rgba[:, 3] * ell, 0.0)
+        e = np.exp(-tau)
+        a = -np.expm1(-tau)
+        C[act] += (T[act] * a)[:, None] * rgba[:, :3]
+        T[act] *= e
+        nsamp[act] += valid
+        last = s >= s1[act]
+        for i, th in enumerate(thetas):
+            new = ~stopped[i][act] & (last | (th < 1.0) & valid & (1.0 - T[act] >= th))
+            rows = act[new]
+            keep[i][0][rows] = C[rows]
+            keep[i][1][rows] = T[rows]
+            keep[i][2][rows] = nsamp[rows]
+            stopped[i][rows] = True
+        act = act[~np.all([st[act] for st in stopped], axis=0)]
+        k += 1
+    out = []
+    for Ck, Tk, nk in keep:
+        rgba = np.zeros((R, 4))
+        rgba[:, :3] = Ck
+        rgba[:, 3] = np.where(hit, 1.0 - Tk, 0.0)
+        out.append((rgba, np.where(hit, t_in, np.inf), nk))
+    return out
+
+
+def render_brick_thresholds(data, stored_lo, dims, owned_lo, owned_hi, tf, params, cam, px, py, thetas,
+                            chunk=1 << 16):
+    """``render_brick`` on the pixels (px, py) for several termination thresholds in
+    one march per ray (``march_rays_thresholds``); a list of (rgba, depth, samples)."""
+    px = np.asarray(px)
+    py = np.asarray(py)
+    R = px.size
+    res = [(np.empty((R, 4)), np.empty(R), np.empty(R, dtype=np.int64)) for _ in thetas]
+    for c0 in range(0, R, chunk):
+        c1 = min(R, c0 + chunk)
+        o, d = camera_rays(cam, px[c0:c1], py[c0:c1])
+        for (rg, dp, ns), (r2, d2, n2) in zip(res, march_rays_thresholds(
+                data, stored_lo, dims, owned_lo, owned_hi, tf, params, o, d, thetas)):
+            rg[c0:c1], dp[c0:c1], ns[c0:c1] = r2, d2, n2
+    return res
+
+
 def render_brick(data, stored_lo, dims, owned_lo, owned_hi, tf, params, cam, px=None, py=None,
                  chunk=1 << 16):
     """Render one brick's partial frame (or a pixel subset of it).

@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
                                                              const float4* __restrict__ tf,
                                                              const float4* __restrict__ grad_out,
                                                              const double* __restrict__ ws,
-                                                             float* __restrict__ gvol, float* __restrict__ gtf,
+                                                             float* __restrict__ gvol, double* __restrict__ gtf,
                                                              int tiles_x, int tiles_per_cam) {
   extern __shared__ float4 lds[];
   float4* tfb = lds;
@@ -307,8 +307,21 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
     float v = 0.f;
 #pragma unroll
     for (int rep = 0; rep < kTfRep; ++rep) v += gt[rep * rstride + i];
-    if (v != 0.f) atomicAdd(gtf + i, v);
+    // the workgroups' partial sums meet in FP64, so an entry's error is that of
+    // one workgroup's FP32 sum, not of thousands of rounded additions
+    if (v != 0.f) atomicAdd(gtf + i, (double)v);
   }
+}
+
+__global__ void fill_f64_kernel(double* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// grad_tf += the FP64 sums (rounded once to FP32)
+__global__ void add_f64_to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] += (float)src[i];
 }
 
 static int max_segments(const int64_t dims[3], float step) {
@@ -446,9 +459,16 @@ dpr_status dpr_render_backward(dpr_device dev, const float* volume, const int64_
   if ((s = cam_table(dev, cams, n, &dc)) != DPR_OK) return s;
   const int tx = (g.W + 15) / 16, ty = (g.H + 15) / 16;
   dim3 grid((unsigned)(tx * ty * n));
+  if (!dev->tf_grad64 && (s = dev_alloc((void**)&dev->tf_grad64, 4 * kMaxTF * sizeof(double),
+                                           "transfer-function gradient sums")) != DPR_OK)
+    return s;
+  const int nt = 4 * n_tf;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((nt + 255) / 256), dim3(256), 0, dev->stream, dev->tf_grad64, nt);
   size_t lds = 2 * sizeof(float4) * (size_t)n_tf + sizeof(float) * (size_t)kTfRep * (4 * n_tf + 1);
   hipLaunchKernelGGL(train_backward_kernel, grid, dim3(256), lds, dev->stream, g, dc, volume, (const float4*)tf,
-                     (const float4*)grad_rgba, (const double*)ws, grad_volume, grad_tf, tx, tx * ty);
+                     (const float4*)grad_rgba, (const double*)ws, grad_volume, dev->tf_grad64, tx, tx * ty);
+  hipLaunchKernelGGL(add_f64_to_f32_kernel, dim3((nt + 255) / 256), dim3(256), 0, dev->stream, dev->tf_grad64,
+                     grad_tf, nt);
   DPR_HIP(hipGetLastError());
   return DPR_OK;
 }

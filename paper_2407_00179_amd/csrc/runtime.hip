@@ -366,6 +366,7 @@ static void device_drop(dpr_device d) {
   dev_free(d->fix_count);
   dev_free(d->fix_list);
   dev_free(d->comp_prior);
+  dev_free(d->tf_grad64);
   delete d;
 }
 

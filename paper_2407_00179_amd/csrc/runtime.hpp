@@ -57,6 +57,8 @@ struct dpr_device_t {
   int* fix_list = nullptr;
   size_t fix_cap = 0;
   float* comp_prior = nullptr;  // sampled nearest depth per source (kCompPriorFloats)
+  // FP64 sums of the transfer-function gradient across workgroups (dpr_render_backward)
+  double* tf_grad64 = nullptr;
   // device address of the library's fixed scratch array on this GPU
   // (dpr_composite_noalloc), looked up when the handle is created
   void* noalloc_scratch = nullptr;

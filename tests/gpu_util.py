@@ -76,6 +76,80 @@ def check_bracketed(got_rgba, got_depth, got_n, oracle_at, ert, tol, what):
     return err
 
 
+def pc10_subset(cam, dims, seed, stride=8, tiles=4, tile=64):
+    """Pixel sample of the full-size checks: every stride-th pixel in x and y of the
+    whole frame plus `tiles` full tile x tile blocks placed (seeded) where the
+    volume's box projects -- found from the camera geometry by the oracle's slab
+    test on a coarse pixel grid, not from any rendered frame."""
+    W, H = cam.width, cam.height
+    ys, xs = np.mgrid[0:H:16, 0:W:16]
+    o, d = oracle.camera_rays(cam, xs.ravel(), ys.ravel())
+    h = 1.0 / max(dims)
+    _, _, hit = oracle.clip_box(o, d, np.zeros(3), np.array(dims, dtype=np.float64) * h)
+    hx, hy = xs.ravel()[hit], ys.ravel()[hit]
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:H:stride, 0:W:stride]
+    px, py = [xx.ravel()], [yy.ravel()]
+    for _ in range(tiles):
+        k = int(rng.integers(0, hx.size))
+        tx = int(np.clip(hx[k] - tile // 2, 0, W - tile))
+        ty = int(np.clip(hy[k] - tile // 2, 0, H - tile))
+        ty_, tx_ = np.mgrid[ty:ty + tile, tx:tx + tile]
+        px.append(tx_.ravel())
+        py.append(ty_.ravel())
+    lin = np.unique(np.concatenate(py) * W + np.concatenate(px))
+    return (lin % W).astype(np.int64), (lin // W).astype(np.int64)
+
+
+def oracle_bracket(data, stored_lo, dims, lo, hi, tf, prm, cam, px, py):
+    """The oracle's partial fragments at the termination thresholds theta - delta and
+    theta + delta (or at theta when early termination is off), from one march per
+    ray; returned as a lookup usable by check_bracketed."""
+    thetas = [prm.ert] if prm.ert >= 1.0 else [prm.ert - ERT_DELTA, prm.ert + ERT_DELTA]
+    p = oracle.RenderParams(prm.step_voxels, 1.0, prm.density, prm.tf_lo, prm.tf_hi)
+    res = oracle.render_brick_thresholds(data, stored_lo, dims, lo, hi, tf, p, cam, px, py, thetas)
+    table = dict(zip(thetas, res))
+    return lambda th: table[th]
+
+
+def check_partials_and_frame(dpr, dev, w, bricks, dims, tf, prm, cam, px, py, tol, what, frame=None):
+    """Every brick's partial frame (dpr_render_partial, the persistent kernel)
+    against the bracketed oracle on the pixel sample; then the composited frame
+    (a) against the oracle's compositor applied to the GPU's own partials, on every
+    sampled pixel, and (b) against the oracle's composite of the oracle's partials
+    on the sampled pixels where no brick's termination step is ambiguous.
+    `bricks` are synth Bricks (their stored data and boxes)."""
+    sel = py * cam.width + px
+    fr = dpr.Frame(dev, cam.width, cam.height)
+    g_r, g_z, o_r, o_z, amb = [], [], [], [], np.zeros(px.size, dtype=bool)
+    for i, b in enumerate(bricks):
+        w.render_partial(i, fr)
+        r, z, _ = frame_np(fr)
+        at = oracle_bracket(b.data, b.stored_lo, dims, b.lo, b.hi, tf, prm, cam, px, py)
+        check_bracketed(r[sel], z[sel], None, at, prm.ert, tol, f"{what} brick {i}")
+        lo_r = at(prm.ert if prm.ert >= 1.0 else prm.ert - ERT_DELTA)
+        hi_r = at(prm.ert if prm.ert >= 1.0 else prm.ert + ERT_DELTA)
+        amb |= np.any(lo_r[0] != hi_r[0], axis=1)
+        g_r.append(r[sel])
+        g_z.append(z[sel])
+        o_r.append(lo_r[0])
+        o_z.append(lo_r[1])
+    fr.release()
+    got, gz, _ = frame_np(frame)
+    got, gz = got[sel], gz[sel]
+    mine, mz = oracle.composite(np.stack(g_r), np.stack(g_z))
+    err_a = np.max(np.abs(got - mine))
+    assert err_a <= tol, f"{what}: composite of the GPU partials differs by {err_a:.3e}"
+    assert np.array_equal(gz, mz.astype(np.float32).astype(np.float64)), f"{what}: composite depth"
+    want, wz = oracle.composite(np.stack(o_r), np.stack(o_z))
+    ok = ~amb
+    err_b = np.max(np.abs(got[ok] - want[ok])) if ok.any() else 0.0
+    log(f"  {what}: frame vs oracle compositor on GPU partials {err_a:.3e}; vs oracle composite on "
+        f"{np.count_nonzero(ok)} unambiguous of {px.size} pixels {err_b:.3e} ({np.count_nonzero(amb)} ambiguous)")
+    assert err_b <= tol, f"{what}: composite vs oracle {err_b:.3e}"
+    return err_b
+
+
 def tf_alpha_max(tf, ranges, lo=0.0, hi=1.0, chunk=1 << 15):
     """FP64 largest table opacity over each value range [min, max] (..., 2): the
     table is piecewise linear, so the maximum lies at an end or at a knot inside."""

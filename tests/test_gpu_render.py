@@ -6,9 +6,9 @@ import pytest
 import oracle
 from oracle import RenderParams
 from synth import (Camera, even_split, extract_brick, get_config, kd_split, make_blobs, make_tf, make_volume_small,
-                   orbit_camera, pixel_subset)
-from tests.gpu_util import (TOL_F16, TOL_F32, check_bracketed, check_majorants, frame_np, log, make_world,
-                            oracle_brick)
+                   orbit_camera)
+from tests.gpu_util import (TOL_F16, TOL_F32, check_bracketed, check_majorants, check_partials_and_frame, frame_np,
+                            log, make_world, oracle_brick, pc10_subset)
 
 pytestmark = pytest.mark.gpu
 
@@ -291,9 +291,11 @@ def test_step_and_camera_variants(gpu_lib, dpr):
 
 
 def test_cfg2_full_size_sampled(gpu_lib, dpr):
-    """512^3 FP32 split 2x2x2 (257^3 stored bricks), 1024^2: sampled pixels against
-    the oracle, the full frame against the GPU's own unsplit render (ERT off)."""
-    from synth import white_noise  # noqa: F401
+    """512^3 FP32 split 2x2x2 (257^3 stored bricks), 1024^2, early termination off
+    and at 0.99: on every 8th pixel plus four 64x64 tiles, every brick's partial
+    against the bracketed oracle and the composited frame against the oracle's
+    composite (on pixels no brick's termination makes ambiguous); with termination
+    off, the whole frame against the GPU's own unsplit render."""
     cfg = get_config("cfg2")
     dims = cfg.dims
     blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
@@ -301,22 +303,19 @@ def test_cfg2_full_size_sampled(gpu_lib, dpr):
     vol = make_volume_small(dims, blobs, cfg.seeds["volume"], cfg.noise_amp)
     tf = make_tf(cfg.seeds["tf"])
     cam = orbit_camera(dims, *cfg.image)
-    px, py = pixel_subset(*cfg.image, stride=32, tiles=2, tile=32, seed=7)
+    px, py = pc10_subset(cam, dims, seed=7)
     boxes = even_split(dims, cfg.parts)
+    bricks = [extract_brick(vol, dims, lo, hi, 1) for lo, hi in boxes]
     for ert in (1.0, cfg.ert):
         prm = RenderParams(cfg.step_voxels, ert, cfg.density)
         log(f"cfg2 ert {ert}: building world")
         w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam)
         out = dpr.Frame(gpu_lib, *cfg.image)
         w.render_frame(out)
-        got, gz, _ = frame_np(out)
-        sel = py * cfg.image[0] + px
-        orc = [oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py) for lo, hi in boxes]
-        want, wz = oracle.composite(np.stack([o[0] for o in orc]), np.stack([o[1] for o in orc]))
-        err = np.max(np.abs(got[sel] - want))
-        log(f"  cfg2 composite vs oracle on {sel.size} pixels: {err:.3e}")
+        check_partials_and_frame(dpr, gpu_lib, w, bricks, dims, tf, prm, cam, px, py, TOL_F32, f"cfg2 ert {ert}",
+                                 frame=out)
         if ert >= 1.0:
-            assert err <= TOL_F32
+            got, _, _ = frame_np(out)
             wu = make_world(dpr, gpu_lib, vol, dims, [((0, 0, 0), dims)], tf, prm, cam)
             un = dpr.Frame(gpu_lib, *cfg.image)
             wu.render_partial(0, un)
@@ -325,15 +324,4 @@ def test_cfg2_full_size_sampled(gpu_lib, dpr):
             log(f"  cfg2 GPU split invariant (full frame): {inv:.3e}")
             assert inv <= TOL_F32
             wu.release()
-        else:
-            assert err <= 2 * (1 - ert) + TOL_F32
-            # per-brick partials against the bracketed oracle on the sample
-            for i in (0, 5):
-                lo, hi = boxes[i]
-                fr = dpr.Frame(gpu_lib, *cfg.image, counts=True)
-                w.render_partial(i, fr)
-                r, z, n = frame_np(fr)
-                check_bracketed(r[sel], z[sel], n[sel],
-                                lambda th: oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, th),
-                                ert, TOL_F32, f"cfg2 brick {i}")
         w.release()

@@ -9,7 +9,7 @@ from scipy import integrate
 import oracle
 from oracle import RenderParams
 from oracle import brute
-from synth import Camera, orbit_camera
+from synth import Camera, extract_brick, make_blobs, make_tf, make_volume_small, orbit_camera
 from tests.helpers import axis_camera, constant_tf, diag_camera, linear_alpha_tf, random_volume, rand_tf
 
 
@@ -231,3 +231,26 @@ def test_ert_stops_once_threshold_reached():
     k = math.ceil(-math.log(0.1) / 2.5)
     assert ns[0] == k
     assert abs(rgba[0, 3] - (1 - math.exp(-2.5 * k))) < 1e-14
+
+
+def test_thresholds_in_one_march_equal_separate_marches():
+    """render_brick_thresholds (one march, several termination thresholds) gives
+    exactly what render_brick gives at each threshold alone, on a split brick."""
+    dims = (40, 36, 30)
+    vol = make_volume_small(dims, make_blobs(dims, 5, 6, (0.08, 0.25)), 6, 0.02)
+    tf = make_tf(2001)
+    cam = orbit_camera(dims, 48, 40)
+    lo, hi = (0, 10, 0), (25, 36, 30)
+    b = extract_brick(vol, dims, lo, hi, 1)
+    py, px = np.mgrid[0:40, 0:48]
+    px, py = px.ravel(), py.ravel()
+    thetas = [0.99 - 1e-4, 0.99 + 1e-4, 0.5, 1.0]
+    prm = oracle.RenderParams(0.5, 1.0, 30.0)
+    res = oracle.render_brick_thresholds(b.data, b.stored_lo, dims, lo, hi, tf, prm, cam, px, py, thetas)
+    terminated = 0
+    for th, (r, z, n) in zip(thetas, res):
+        p = oracle.RenderParams(0.5, th, 30.0)
+        r2, z2, n2 = oracle.render_brick(b.data, b.stored_lo, dims, lo, hi, tf, p, cam, px, py)
+        assert np.array_equal(r, r2) and np.array_equal(z, z2) and np.array_equal(n, n2)
+        terminated += int(np.count_nonzero(r[:, 3] >= th))
+    assert terminated > 0
