@@ -16,12 +16,13 @@ struct McBrick {
   const void* linear;
   BrickG view;
   float2* ranges;
+  float2* partial;  // 2 per macrocell: scratch of the commit
   bool f16;
   bool half16;  // FP16 blocked copy of 2-byte voxels (else 4-byte voxel pairs)
 };
 // Blocked copy and macrocell ranges of several bricks in one pass over their
 // linear stored copies.
-hipError_t launch_commit(const McBrick* bricks, int n, int mc, hipStream_t st);
+hipError_t launch_commit(const McBrick* bricks, int n, int mc, int cu_count, hipStream_t st);
 // Majorants of up to kMajJobs bricks in one launch (passed by value).
 constexpr int kMajJobs = 32;
 struct MajJobs {

@@ -557,7 +557,9 @@ dpr_status dpr_world_commit(dpr_world w) {
       b.ranges = nullptr;
       b.maj = nullptr;
       size_t cnt = (size_t)md[0] * md[1] * md[2];
-      st = dev_alloc((void**)&b.ranges, cnt * sizeof(float2), "macrocell ranges");
+      // the ranges, then the commit's two partial ranges per macrocell (the
+      // x-windows that straddle two commit waves' column spans)
+      st = dev_alloc((void**)&b.ranges, 3 * cnt * sizeof(float2), "macrocell ranges");
       if (st != DPR_OK) return st;
       st = dev_alloc((void**)&b.maj, cnt * sizeof(float), "macrocell majorants");
       if (st != DPR_OK) return st;
@@ -567,8 +569,10 @@ dpr_status dpr_world_commit(dpr_world w) {
     b.maj_tf_version = 0;
   }
   std::vector<McBrick> mcb;
-  for (auto& b : w->bricks) mcb.push_back({b.linear, b.device_view(false), b.ranges, b.dtype == DPR_F16, b.half16});
-  DPR_HIP(launch_commit(mcb.data(), (int)mcb.size(), mc, w->dev->stream));
+  for (auto& b : w->bricks)
+    mcb.push_back({b.linear, b.device_view(false), b.ranges, b.ranges + (size_t)b.mdim[0] * b.mdim[1] * b.mdim[2],
+                   b.dtype == DPR_F16, b.half16});
+  DPR_HIP(launch_commit(mcb.data(), (int)mcb.size(), mc, w->dev->cu_count, w->dev->stream));
   // (stream-ordered: later renders on the device stream see the new data; the
   // host does not wait)
   w->committed = true;

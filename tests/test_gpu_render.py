@@ -7,7 +7,7 @@ import oracle
 from oracle import RenderParams
 from synth import (Camera, even_split, extract_brick, get_config, kd_split, make_blobs, make_tf, make_volume_small,
                    orbit_camera)
-from tests.gpu_util import (TOL_F16, TOL_F32, check_bracketed, check_majorants, check_partials_and_frame, frame_np,
+from tests.gpu_util import (ERT_DELTA, TOL_F16, TOL_F32, check_bracketed, check_majorants, check_partials_and_frame, frame_np,
                             log, make_world, oracle_brick, pc10_subset)
 
 pytestmark = pytest.mark.gpu
@@ -96,7 +96,6 @@ def test_bricks_partials_and_frame(gpu_lib, dpr, split, ert):
     # versus the oracle's composite of the oracle's partials
     orc = [oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py) for lo, hi in boxes]
     want, wz = oracle.composite(np.stack([o[0] for o in orc]), np.stack([o[1] for o in orc]))
-    tol = TOL_F32 if ert >= 1.0 else 2 * TOL_F32 + 0.0
     if ert >= 1.0:
         err = np.max(np.abs(got - want))
         assert err <= TOL_F32, err
@@ -112,11 +111,24 @@ def test_bricks_partials_and_frame(gpu_lib, dpr, split, ert):
         assert np.array_equal(np.isfinite(gz), fin) and np.allclose(gz[fin], guz[fin], rtol=3e-7, atol=0)
         wu.release()
     else:
-        # per-brick ERT: composite within 2 (1 - theta) of the oracle's composite
-        # and each partial already matched its bracket
-        err = np.max(np.abs(got - want))
-        log(f"  composite (ERT {ert}) vs oracle composite {err:.3e}")
-        assert err <= 2 * (1 - ert) + tol
+        # per-brick ERT: every partial already matched its bracket.  Where no
+        # brick's termination step is ambiguous (its partial is the same at
+        # theta -+ delta) the frame matches the oracle's composite at the FP32 bar;
+        # everywhere it matches the oracle compositor applied to the GPU partials.
+        amb = np.zeros(px.size, dtype=bool)
+        for lo, hi in boxes:
+            a = oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, ert - ERT_DELTA)[0]
+            b = oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py, ert + ERT_DELTA)[0]
+            amb |= np.any(a != b, axis=1)
+        ok = ~amb
+        err = np.max(np.abs(got[ok] - want[ok]))
+        pr = [frame_np(f) for f in parts]
+        mine, _ = oracle.composite(np.stack([r for r, _, _ in pr]), np.stack([z for _, z, _ in pr]))
+        err_g = np.max(np.abs(got - mine))
+        log(f"  composite (ERT {ert}) vs oracle composite {err:.3e} on {np.count_nonzero(ok)} unambiguous of "
+            f"{px.size} pixels; vs oracle compositor on the GPU partials {err_g:.3e}")
+        assert err <= TOL_F32 and err_g <= TOL_F32
+        assert np.count_nonzero(ok) >= px.size // 2
     w.release()
 
 
