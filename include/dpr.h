@@ -102,6 +102,12 @@ typedef struct {
 
 const char* dpr_last_error(void);
 const char* dpr_version(void);
+/* Allocation counters of this process (diagnostics, needs no GPU): `allocations`
+ * = device and pinned host allocations attempted so far (the count that the
+ * environment setting DPR_FAULT_INJECT=alloc:N refers to: the N-th attempt then
+ * fails with DPR_ERR_OUT_OF_MEMORY), `live` = those not yet freed.  Either
+ * pointer may be NULL.                                                           */
+dpr_status dpr_alloc_stats(int64_t* allocations, int64_t* live);
 
 /* ---------------------------------------------------------------- device */
 /* Bind GPU `hip_device` and the HIP stream `hip_stream` (NULL: the null stream).

@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdpr.so")
+# DPR_LIBRARY names another build of the same library (the test suite uses it for a
+# build whose host code carries sanitizers)
+LIB_PATH = os.environ.get("DPR_LIBRARY") or os.path.join(HERE, "libdpr.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_00179_amd.build` "
@@ -64,6 +66,7 @@ I32x3 = C.c_int32 * 3
 _SIGS = {
     "dpr_last_error": ([], C.c_char_p),
     "dpr_version": ([], C.c_char_p),
+    "dpr_alloc_stats": ([C.POINTER(C.c_int64), C.POINTER(C.c_int64)], C.c_int),
     "dpr_device_create": ([C.c_int, P, C.POINTER(P)], C.c_int),
     "dpr_device_set_stream": ([P, P], C.c_int),
     "dpr_device_sync": ([P], C.c_int),

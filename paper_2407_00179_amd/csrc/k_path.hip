@@ -582,7 +582,7 @@ void path_state_free(PathState* p) {
   dev_free(p->d_sgrid);
   dev_free(p->d_count);
   dev_free(p->d_stats);
-  if (p->h_count) (void)hipHostFree(p->h_count);
+  host_free(p->h_count);
   delete p;
 }
 
@@ -660,7 +660,7 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
   if (!ps->d_count) {
     if ((s = dev_alloc((void**)&ps->d_count, 4 * sizeof(int), "path pool sizes and cursors")) != DPR_OK) return s;
     if ((s = dev_alloc((void**)&ps->d_stats, 5 * sizeof(unsigned long long), "path stats")) != DPR_OK) return s;
-    DPR_HIP(hipHostMalloc((void**)&ps->h_count, 2 * sizeof(int), hipHostMallocDefault));
+    if ((s = host_alloc((void**)&ps->h_count, 2 * sizeof(int), "path pool sizes (host)")) != DPR_OK) return s;
   }
   // owner table of 16^3-cell blocks, rebuilt when bricks were added
   int od[3];

@@ -1,6 +1,7 @@
 // C ABI implementation: devices, worlds, bricks, frames, validation and the
 // per-brick render / composite entry points.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -51,24 +52,52 @@ bool log_enabled() {
   return on == 1;
 }
 
-static long g_alloc_count = 0;
+static std::atomic<long> g_alloc_count{0};  // allocations attempted
+static std::atomic<long> g_alloc_live{0};   // allocations not yet freed
+
+static bool injected_failure(long n) {
+  const char* fi = getenv("DPR_FAULT_INJECT");
+  return fi && strncmp(fi, "alloc:", 6) == 0 && atol(fi + 6) == n;
+}
 
 dpr_status dev_alloc(void** p, size_t bytes, const char* what) {
-  ++g_alloc_count;
-  const char* fi = getenv("DPR_FAULT_INJECT");
-  if (fi && strncmp(fi, "alloc:", 6) == 0 && atol(fi + 6) == g_alloc_count)
-    return fail(DPR_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (allocation %ld)", what, g_alloc_count);
+  *p = nullptr;
+  const long n = ++g_alloc_count;
+  if (injected_failure(n)) return fail(DPR_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (allocation %ld)", what, n);
   hipError_t e = hipMalloc(p, bytes ? bytes : 1);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
     return fail(DPR_ERR_OUT_OF_MEMORY, "%s: hipMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
   }
+  ++g_alloc_live;
   return DPR_OK;
 }
 
 void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  (void)hipFree(p);
+  --g_alloc_live;
+}
+
+dpr_status host_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  const long n = ++g_alloc_count;
+  if (injected_failure(n)) return fail(DPR_ERR_OUT_OF_MEMORY, "%s: injected allocation failure (allocation %ld)", what, n);
+  hipError_t e = hipHostMalloc(p, bytes ? bytes : 1, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(DPR_ERR_OUT_OF_MEMORY, "%s: hipHostMalloc(%zu) failed: %s", what, bytes, hipGetErrorString(e));
+  }
+  ++g_alloc_live;
+  return DPR_OK;
+}
+
+void host_free(void* p) {
+  if (!p) return;
+  (void)hipHostFree(p);
+  --g_alloc_live;
 }
 
 // ---------------------------------------------------------------- geometry helpers
@@ -211,11 +240,12 @@ dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, co
       if (j->second.last_use < victim->second.last_use) victim = j;
     DPR_HIP(hipStreamSynchronize(dev->stream));
     dev_free(victim->second.dev);
-    (void)hipHostFree(victim->second.host);
+    host_free(victim->second.host);
     dev->comp_cache.erase(victim);
   }
   CompEntry e;
-  DPR_HIP(hipHostMalloc((void**)&e.host, sizeof(CompTable), hipHostMallocDefault));
+  dpr_status hs = host_alloc((void**)&e.host, sizeof(CompTable), "composite table (host)");
+  if (hs != DPR_OK) return hs;
   memset(e.host, 0, sizeof(CompTable));
   std::vector<int> order(k);
   std::iota(order.begin(), order.end(), 0);
@@ -229,13 +259,13 @@ dpr_status comp_table(dpr_device dev, const std::vector<const float4*>& rgba, co
   }
   dpr_status st = dev_alloc((void**)&e.dev, sizeof(CompTable), "composite table");
   if (st != DPR_OK) {
-    (void)hipHostFree(e.host);
+    host_free(e.host);
     return st;
   }
   hipError_t he = hipMemcpyAsync(e.dev, e.host, sizeof(CompTable), hipMemcpyHostToDevice, dev->stream);
   if (he != hipSuccess) {
     dev_free(e.dev);
-    (void)hipHostFree(e.host);
+    host_free(e.host);
     return hip_fail(he, "hipMemcpyAsync(composite table)");
   }
   e.last_use = ++dev->use_clock;
@@ -305,6 +335,12 @@ extern "C" {
 const char* dpr_last_error(void) { return g_last_error.c_str(); }
 const char* dpr_version(void) { return "dpr 0.1 gfx950"; }
 
+dpr_status dpr_alloc_stats(int64_t* allocations, int64_t* live) {
+  if (allocations) *allocations = g_alloc_count.load();
+  if (live) *live = g_alloc_live.load();
+  return DPR_OK;
+}
+
 // ---------------------------------------------------------------- device
 dpr_status dpr_device_create(int hip_device, void* hip_stream, dpr_device* out) {
   if (!out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_device_create: out is NULL");
@@ -361,7 +397,7 @@ static void device_drop(dpr_device d) {
   (void)hipStreamSynchronize(d->stream);
   for (auto& kv : d->comp_cache) {
     dev_free(kv.second.dev);
-    (void)hipHostFree(kv.second.host);
+    host_free(kv.second.host);
   }
   dev_free(d->fix_count);
   dev_free(d->fix_list);
@@ -405,7 +441,7 @@ void dpr_world_release(dpr_world w) {
     if (b) batch_state_free(b);
   if (w->path) path_state_free(w->path);
   dev_free(w->tf_dev);
-  if (w->tf_host) (void)hipHostFree(w->tf_host);
+  host_free(w->tf_host);
   if (w->tf_ev) (void)hipEventDestroy(w->tf_ev);
   dpr_device d = w->dev;
   delete w;
@@ -630,7 +666,8 @@ dpr_status dpr_set_transfer_function(dpr_world w, const float* rgba, int32_t n, 
   // does not wait for the device; the staging buffer is reused once the previous
   // upload has been consumed
   if (!w->tf_host) {
-    DPR_HIP(hipHostMalloc((void**)&w->tf_host, kMaxTF * sizeof(float4), hipHostMallocDefault));
+    dpr_status hs = host_alloc((void**)&w->tf_host, kMaxTF * sizeof(float4), "transfer function staging");
+    if (hs != DPR_OK) return hs;
     DPR_HIP(hipEventCreateWithFlags(&w->tf_ev, hipEventDisableTiming));
   }
   if (w->tf_ev_pending) DPR_HIP(hipEventSynchronize(w->tf_ev));

@@ -27,10 +27,13 @@ bool log_enabled();
     if (e_ != hipSuccess) return ::dpr::hip_fail(e_, #call);   \
   } while (0)
 
-// Device allocation with optional fault injection (DPR_FAULT_INJECT=alloc:N makes
-// the N-th allocation of the process fail with DPR_ERR_OUT_OF_MEMORY).
+// Device and pinned host allocation, counted (dpr_alloc_stats) and with optional
+// fault injection: DPR_FAULT_INJECT=alloc:N makes the N-th allocation of the
+// process (of either kind) fail with DPR_ERR_OUT_OF_MEMORY.
 dpr_status dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void* p);
+dpr_status host_alloc(void** p, size_t bytes, const char* what);
+void host_free(void* p);
 
 struct CompEntry {
   CompTable* dev = nullptr;

@@ -41,6 +41,13 @@ def test_version_and_error_strings(N):
     assert isinstance(N.lib.dpr_last_error(), bytes)
 
 
+def test_allocation_counters_answer_without_gpu(N):
+    a, live = C.c_int64(-1), C.c_int64(-1)
+    assert N.lib.dpr_alloc_stats(C.byref(a), C.byref(live)) == 0
+    assert a.value >= 0 and 0 <= live.value <= a.value
+    assert N.lib.dpr_alloc_stats(None, None) == 0
+
+
 def test_device_create_without_gpu_reports_device_error(N):
     import torch
     if torch.cuda.is_available():
@@ -151,5 +158,6 @@ def test_missing_library_fails_loudly(tmp_path):
     dst = tmp_path / "paper_2407_00179_amd"
     shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "_build", "__pycache__"))
     code = "import sys; sys.path.insert(0, %r); import paper_2407_00179_amd" % str(tmp_path)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    env = {k: v for k, v in os.environ.items() if k != "DPR_LIBRARY"}
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env)
     assert r.returncode != 0 and "libdpr.so" in r.stderr
