@@ -157,6 +157,17 @@ dpr_status dpr_world_add_brick(dpr_world, const void* voxels, dpr_dtype dtype, i
  * Gaps between bricks are allowed and render empty.                             */
 dpr_status dpr_world_commit(dpr_world);
 
+/* Free every brick's linear stored copy (the one dpr_world_add_brick made) once
+ * the world is committed, so that a brick occupies only its blocked copy: 4 bytes
+ * a voxel for FP32 and for FP16 voxel pairs, 2 for the FP16 2-byte layout (plus
+ * 24 bytes a macrocell).  Waits for the device stream.  Afterwards
+ * dpr_world_commit with nothing to rebuild returns DPR_OK at once; one that must
+ * rebuild (bricks added, or the macrocell edge or the FP16 layout flags changed)
+ * fails with DPR_ERR_INVALID_STATE, as does dpr_render_path when it must rebuild
+ * its block majorants (after a commit or a transfer-function change).  Fails
+ * with DPR_ERR_INVALID_STATE on a world that is not committed.                  */
+dpr_status dpr_world_release_linear(dpr_world);
+
 /* Transfer function: n_entries RGBA floats (host), entry i at value
  * value_lo + i (value_hi - value_lo)/(n_entries - 1); RGB is emitted colour,
  * A is normalised extinction; extinction per world unit = density_scale * A.

@@ -217,6 +217,10 @@ class World:
     def commit(self):
         check(lib.dpr_world_commit(self.h))
 
+    def release_linear(self):
+        """Free the bricks' linear copies of a committed world (see dpr_world_release_linear)."""
+        check(lib.dpr_world_release_linear(self.h))
+
     def set_transfer_function(self, tf, lo=0.0, hi=1.0, density=20.0):
         t = np.ascontiguousarray(tf, dtype=np.float32)
         check(lib.dpr_set_transfer_function(self.h, C.c_void_p(t.ctypes.data), t.shape[0], lo, hi, density))

@@ -740,6 +740,10 @@ extern "C" dpr_status dpr_render_path(dpr_world w, const dpr_path_params* prm, d
     }
     DPR_HIP(hipMemsetAsync(ps->d_lo, 0xff, n_own * sizeof(uint32_t), st));
     DPR_HIP(hipMemsetAsync(ps->d_hi, 0, n_own * sizeof(uint32_t), st));
+    for (const auto& b : w->bricks)
+      if (!b.linear)
+        return fail(DPR_ERR_INVALID_STATE,
+                    "dpr_render_path: the block majorants need the bricks' linear copies, which were released");
     for (const auto& b : w->bricks) {
       BlkRangeJob J{};
       J.vox = b.linear;

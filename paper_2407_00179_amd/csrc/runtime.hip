@@ -561,6 +561,13 @@ dpr_status dpr_world_commit(dpr_world w) {
   if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_commit: NULL world");
   dpr_status st = check_partition(w);
   if (st != DPR_OK) return st;
+  for (const auto& b : w->bricks)
+    if (!b.linear) {
+      if (w->committed) return DPR_OK;  // nothing to rebuild
+      return fail(DPR_ERR_INVALID_STATE,
+                  "dpr_world_commit: the linear copies were released and the bricks, the macrocell edge or the FP16 "
+                  "layout flags changed since the last commit");
+    }
   const int mc = w->params.macrocell_cells;
   // FP16 layout, one for the whole world (the batched kernel reads every brick the
   // same way): 2-byte voxels when asked for (or 64-bit offsets were), or when some
@@ -613,6 +620,17 @@ dpr_status dpr_world_commit(dpr_world w) {
   // host does not wait)
   w->committed = true;
   ++w->commit_version;
+  return DPR_OK;
+}
+
+dpr_status dpr_world_release_linear(dpr_world w) {
+  if (!w) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_release_linear: NULL world");
+  if (!w->committed) return fail(DPR_ERR_INVALID_STATE, "dpr_world_release_linear: world not committed");
+  DPR_HIP(hipStreamSynchronize(w->dev->stream));  // the commit reads them
+  for (auto& b : w->bricks) {
+    dev_free(b.linear);
+    b.linear = nullptr;
+  }
   return DPR_OK;
 }
 

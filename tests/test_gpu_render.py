@@ -337,3 +337,43 @@ def test_cfg2_full_size_sampled(gpu_lib, dpr):
             assert inv <= TOL_F32
             wu.release()
         w.release()
+
+
+@pytest.mark.parametrize("flags", [0, 0x10])   # FP16 voxel pairs; FP16 2-byte layout
+def test_release_linear_keeps_renders(gpu_lib, dpr, flags):
+    """After dpr_world_release_linear the frame is the same bits, a commit with
+    nothing to rebuild is a no-op, and one that must rebuild (or a path-tracer
+    block-majorant build) fails with DPR_ERR_INVALID_STATE."""
+    import ctypes as C
+    dims = (72, 64, 56)
+    vol, tf = _small_case(dims, seed=5, dtype=np.float16)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 64, 48)
+    boxes = even_split(dims, (2, 1, 2))
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, flags=flags)
+    f = dpr.Frame(gpu_lib, 64, 48)
+    w.render_frame(f)
+    want = frame_np(f)[:2]
+
+    def live():
+        a, n = C.c_int64(), C.c_int64()
+        dpr.check(dpr.lib.dpr_alloc_stats(C.byref(a), C.byref(n)))
+        return n.value
+
+    before = live()
+    w.release_linear()
+    assert live() == before - len(boxes)
+    for _ in range(2):
+        w.render_frame(f)
+        got = frame_np(f)[:2]
+        assert all(np.array_equal(a, b) for a, b in zip(want, got))
+        w.commit()   # nothing to rebuild
+    with pytest.raises(dpr.DprError) as e:
+        w.render_path(f)
+    assert e.value.status == -2
+    w.set_params(dpr.Params(prm.step_voxels, prm.ert, 8, flags))
+    with pytest.raises(dpr.DprError) as e:
+        w.commit()
+    assert e.value.status == -2
+    f.release()
+    w.release()
