@@ -207,6 +207,17 @@ dpr_status dpr_check_camera(const dpr_camera*);
 dpr_status dpr_world_brick_macrocells(dpr_world, int32_t brick_id, int32_t mc_dims[3], float* ranges,
                                       float* majorant, size_t capacity);
 dpr_status dpr_world_brick_count(dpr_world, int32_t* n);
+/* Read back a committed brick's blocked copy (diagnostics; synchronises).
+ * bdim = blocks per axis, elem_bytes = 4 (FP32 voxels, FP16 voxel pairs: the
+ * halves of voxels x and x + 1, the last voxel of a row paired with itself) or
+ * 2 (FP16 voxels).  Layout: 8^3-voxel blocks, x fastest then y then z; inside a
+ * block the 9 index bits of stored voxel (i, j, k) are, from bit 0: i0 i1 j0 k0
+ * j1 k1 i2 j2 k2 (i, j, k taken mod 8).  Elements of padding voxels beyond the
+ * stored extents are zero.  host may be NULL (only bdim and elem_bytes are
+ * returned); else capacity (bytes) must hold bdim[0] bdim[1] bdim[2] 512
+ * elem_bytes.                                                                     */
+dpr_status dpr_world_brick_blocked(dpr_world, int32_t brick_id, int32_t bdim[3], int32_t* elem_bytes, void* host,
+                                   size_t capacity);
 
 /* ---------------------------------------------------------------- frames */
 dpr_status dpr_frame_create(dpr_device, int32_t width, int32_t height, dpr_frame* out);

@@ -256,6 +256,16 @@ class World:
                                              C.c_void_p(maj.ctypes.data), cnt))
         return ranges, maj
 
+    def blocked_copy(self, brick_id):
+        """(raw bytes of a brick's 8^3-blocked copy as uint8, blocks per axis, element bytes); see dpr_world_brick_blocked."""
+        bd = N.I32x3()
+        eb = C.c_int32()
+        check(lib.dpr_world_brick_blocked(self.h, int(brick_id), bd, C.byref(eb), None, 0))
+        n = bd[0] * bd[1] * bd[2] * 512 * eb.value
+        buf = np.empty(n, dtype=np.uint8)
+        check(lib.dpr_world_brick_blocked(self.h, int(brick_id), bd, C.byref(eb), C.c_void_p(buf.ctypes.data), n))
+        return buf, (bd[0], bd[1], bd[2]), eb.value
+
     def render_partial(self, brick_id, frame: Frame):
         check(lib.dpr_render_partial(self.h, brick_id, frame.h))
 

@@ -77,6 +77,7 @@ _SIGS = {
     "dpr_world_add_brick": ([P, P, C.c_int, C.c_int, I64x3, I64x3, I32x3, I32x3, C.POINTER(C.c_int32)], C.c_int),
     "dpr_world_commit": ([P], C.c_int),
     "dpr_world_release_linear": ([C.c_void_p], C.c_int),
+    "dpr_world_brick_blocked": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p, C.c_size_t], C.c_int),
     "dpr_check_partition": ([I64x3, C.c_int32, P, P, P, P], C.c_int),
     "dpr_check_camera": ([C.POINTER(Camera)], C.c_int),
     "dpr_world_brick_count": ([P, C.POINTER(C.c_int32)], C.c_int),

@@ -662,6 +662,24 @@ dpr_status dpr_world_brick_macrocells(dpr_world w, int32_t id, int32_t md[3], fl
   return DPR_OK;
 }
 
+dpr_status dpr_world_brick_blocked(dpr_world w, int32_t id, int32_t bdim[3], int32_t* elem_bytes, void* host,
+                                   size_t capacity) {
+  if (!w || !bdim || !elem_bytes) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_blocked: NULL argument");
+  if (!w->committed) return fail(DPR_ERR_INVALID_STATE, "dpr_world_brick_blocked: world not committed");
+  if (id < 0 || id >= (int)w->bricks.size())
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_blocked: brick %d does not exist", id);
+  const Brick& b = w->bricks[id];
+  const size_t bytes = (size_t)b.bdim[0] * b.bdim[1] * b.bdim[2] * kBlockVoxels * b.blocked_elem();
+  for (int a = 0; a < 3; ++a) bdim[a] = b.bdim[a];
+  *elem_bytes = (int32_t)b.blocked_elem();
+  if (!host) return DPR_OK;
+  if (capacity < bytes)
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_world_brick_blocked: capacity %zu < %zu bytes", capacity, bytes);
+  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  DPR_HIP(hipMemcpy(host, b.blocked, bytes, hipMemcpyDeviceToHost));
+  return DPR_OK;
+}
+
 dpr_status dpr_set_transfer_function(dpr_world w, const float* rgba, int32_t n, float lo, float hi, float density) {
   if (!w || !rgba) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: NULL argument");
   if (n < 2 || n > kMaxTF) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_set_transfer_function: n_entries %d", n);

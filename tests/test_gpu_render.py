@@ -377,3 +377,55 @@ def test_release_linear_keeps_renders(gpu_lib, dpr, flags):
     assert e.value.status == -2
     f.release()
     w.release()
+
+
+def _deblock(buf, bdim, elem_bytes, sdim):
+    """Element of every stored voxel (z, y, x) of a blocked copy, from the layout's
+    definition: 8^3 blocks x fastest; inside a block the index bits, from bit 0,
+    are i0 i1 j0 k0 j1 k1 i2 j2 k2."""
+    sx, sy, sz = sdim
+    z, y, x = np.meshgrid(np.arange(sz), np.arange(sy), np.arange(sx), indexing="ij")
+    i, j, k = x & 7, y & 7, z & 7
+    within = ((i & 3) | ((j & 1) << 2) | ((k & 1) << 3) | ((j & 2) << 3) | ((k & 2) << 4) | ((i & 4) << 4)
+              | ((j & 4) << 5) | ((k & 4) << 6))
+    blk = ((z >> 3) * bdim[1] + (y >> 3)) * bdim[0] + (x >> 3)
+    return buf.view(np.uint32 if elem_bytes == 4 else np.uint16)[blk * 512 + within]
+
+
+@pytest.mark.parametrize("dims,dtype,flags,mc,ghost,nb", [
+    ((70, 45, 38), np.float32, 0, 16, 1, 5),
+    ((70, 45, 38), np.float16, 0, 2, 3, 5),      # FP16 voxel pairs
+    ((70, 45, 38), np.float16, 0x10, 16, 2, 5),  # FP16 2-byte voxels
+    ((301, 21, 19), np.float16, 0x10, 64, 3, 3),  # several 128-column spans, odd extents
+    ((301, 21, 19), np.float32, 0, 4, 1, 2),
+    ((259, 34, 33), np.float16, 0, 8, 1, 4),
+])
+def test_blocked_copy_bitwise(gpu_lib, dpr, dims, dtype, flags, mc, ghost, nb):
+    """Every stored voxel of every brick's blocked copy, read back and de-blocked
+    on the host, equals the input bit for bit (FP16 pairs: voxel x in the low
+    half, voxel x + 1 -- or x again at the end of a row -- in the high half)."""
+    vol, tf = _small_case(dims, seed=17, nb=4, dtype=dtype)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cam = orbit_camera(dims, 16, 16)
+    boxes = kd_split(dims, nb, seed=11, max_ratio=6.0)
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cam, mc=mc, flags=flags, ghost=ghost)
+    for i, (lo, hi) in enumerate(boxes):
+        b = extract_brick(vol, dims, lo, hi, ghost)
+        data = np.ascontiguousarray(b.data)
+        sdim = (data.shape[2], data.shape[1], data.shape[0])
+        buf, bdim, eb = w.blocked_copy(i)
+        got = _deblock(buf, bdim, eb, sdim)
+        if dtype == np.float32:
+            want = data.view(np.uint32)
+        elif eb == 2:
+            want = data.view(np.uint16)
+        else:
+            h = data.view(np.uint16).astype(np.uint32)
+            nxt = np.concatenate([h[:, :, 1:], h[:, :, -1:]], axis=2)
+            want = h | (nxt << 16)
+        assert eb == (2 if (dtype == np.float16 and flags & 0x10) else 4)
+        assert np.array_equal(got, want), (i, int(np.count_nonzero(got != want)))
+        # padding voxels of the last blocks stay zero
+        el = buf.view(np.uint32 if eb == 4 else np.uint16)
+        assert np.count_nonzero(el) == np.count_nonzero(got)
+    w.release()
