@@ -13,14 +13,17 @@
 // the lanes of the four (y, z) parities, and each x-window's part in the span is
 // reduced through a small wave-private LDS row into one of the macrocell's two
 // partial ranges (a window meets one or two spans); a small second kernel takes
-// their union.  No workgroup barrier is needed.  Only the one-row y aprons of
-// neighbouring macrocells are read twice.  Write ownership: every column belongs
-// to its span, and a (y, y+1) or (z, z+1) row pair to the macrocell whose core
-// [mc m + g, mc (m+1) + g) (the first core extended down to 0, the last up to the
-// stored edge) holds its even row.  A lane reads 8 consecutive voxels of a row
-// with wide loads that need only 4-byte alignment; the rows are visited in quads
-// of 4 x 4 (y, z) rows aligned to the blocked layout, so the stores of one batch
-// fill whole 64-element groups of it.
+// their union.  Only the one-row y aprons of neighbouring macrocells are read
+// twice; a workgroup's four waves (consecutive y macrocells) meet at a barrier
+// after every z stage and sweep their rows in opposite directions (odd y
+// macrocells downwards), so the rows two neighbours share are read by both in
+// the same batch and the second read mostly hits in L2.  Write ownership: every
+// column belongs to its span, and a (y, y+1) or (z, z+1) row pair to the
+// macrocell whose core [mc m + g, mc (m+1) + g) (the first core extended down to
+// 0, the last up to the stored edge) holds its even row.  A lane reads 8
+// consecutive voxels of a row with wide loads that need only 4-byte alignment;
+// the rows are visited in quads of 4 x 4 (y, z) rows aligned to the blocked
+// layout, so the stores of one batch fill whole 64-element groups of it.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -236,8 +239,10 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(4
   while (j + 1 < jobs.n && bid >= jobs.job[j].blocks) bid -= jobs.job[j++].blocks;
   const CmJob& J = jobs.job[j];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int my = (bid % J.ygroups) * kCmWaves + wave;
-  if (my >= J.mdy) return;  // the waves are independent: no barrier follows
+  const int my0 = (bid % J.ygroups) * kCmWaves + wave;
+  const bool active = my0 < J.mdy;  // an idle wave still meets the workgroup's stage barriers
+  const int my = active ? my0 : J.mdy - 1;
+  const bool rev = my & 1;          // odd y macrocells sweep their quads downwards
   const int k = (bid / J.ygroups) % J.spans, sg = bid / (J.ygroups * J.spans);
   const E* __restrict__ src = (const E*)J.src;
   void* __restrict__ dst = J.dst;
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(4
     z_window(s, mz0, mz1, mc, J.gz, sz, b0, b1);
     z_window(s + 1, mz0, mz1, mc, J.gz, sz, c0, c1);
     const int zq0 = st.lo & ~3;
-    const int items = st.hi > st.lo ? 4 * (((st.hi - 1 - zq0) >> 2) + 1) * nyq : 0;  // 4 row groups a quad
+    const int items = active && st.hi > st.lo ? 4 * (((st.hi - 1 - zq0) >> 2) + 1) * nyq : 0;  // 4 row groups a quad
     int yqi = 0, zqi = 0;  // quad of the batch's first row group (quads y fastest)
     for (int i0 = 0; i0 < items; i0 += U) {
       // the loads of U row groups are issued before any of them is used
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(4
           yq = 0;
           ++zq;
         }
-        yy[u] = yq0 + 4 * yq + 2 * (sub & 1);
+        yy[u] = yq0 + 4 * (rev ? nyq - 1 - yq : yq) + 2 * (sub & 1);
         zz[u] = zq0 + 4 * zq + 2 * (sub >> 1);
         const int y = yy[u] + py, z = zz[u] + pz;
         const bool win = y >= Y.ws && y <= Y.we && z >= zw0 && z <= zw1;
@@ -353,7 +358,7 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(4
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
-    if (s - 1 >= mz0) {
+    if (active && s - 1 >= mz0) {
       // macrocell s - 1's window is complete: combine the four (y, z) parities of
       // each column (16 and 32 lanes apart), then reduce each x-window's part in
       // this span
@@ -401,6 +406,7 @@ __global__ __launch_bounds__(64 * kCmWaves) __attribute__((amdgpu_waves_per_eu(4
     A = B;
     B = C;
     C.init();
+    __syncthreads();
   }
 }
 
