@@ -73,6 +73,10 @@ typedef enum { DPR_F32 = 0, DPR_F16 = 1 } dpr_dtype;
  * memory and half the cache lines per sample, more loads per sample; the results
  * are identical.  Changing it un-commits the world.                             */
 #define DPR_FLAG_F16_HALVES 0x10u
+/* batched renders (diagnostics): count how often each queue item is taken and
+ * each of its fragment slots written, for dpr_batch_coverage; the render is then
+ * enqueued directly (no graph replay).  The frames are the same bits.          */
+#define DPR_FLAG_QUEUE_COVERAGE 0x20u
 
 typedef struct dpr_device_t* dpr_device; /* one GPU + one HIP stream              */
 typedef struct dpr_world_t* dpr_world;   /* this rank's bricks + TF + camera      */
@@ -92,7 +96,7 @@ typedef struct {
  * ert_threshold: stop a ray once 1 - T >= threshold; >= 1 disables.
  * macrocell_cells: macrocell edge in cells (power of two in [2, 64]).
  * flags: DPR_FLAG_NO_SKIP, DPR_FLAG_PLAIN, DPR_FLAG_NO_GRAPH (dpr_render_frame),
- * DPR_FLAG_WIDE_OFFSETS, DPR_FLAG_F16_HALVES. */
+ * DPR_FLAG_WIDE_OFFSETS, DPR_FLAG_F16_HALVES, DPR_FLAG_QUEUE_COVERAGE. */
 typedef struct {
   float step_voxels;
   float ert_threshold;
@@ -310,6 +314,14 @@ dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
  * DPR_ERR_INVALID_STATE when the last batched render was a graph replay (or
  * there was none).                                                              */
 dpr_status dpr_batch_timings(dpr_world, float* march_ms, float* composite_ms);
+
+/* Queue coverage of the last batched render, which must have run with
+ * DPR_FLAG_QUEUE_COVERAGE (else DPR_ERR_INVALID_STATE): out[0] = queue items
+ * ((camera, brick, screen tile) triples), out[1] = items taken exactly once,
+ * out[2] = fragment slots (items x tile pixels), out[3] = slots written exactly
+ * once.  A complete render has out[1] == out[0] and out[3] == out[2].
+ * Synchronises.                                                                 */
+dpr_status dpr_batch_coverage(dpr_world, int64_t out[4]);
 
 /* ---------------------------------------------------------------- measurement */
 /* Gather ceiling of the local render (a roofline probe, not part of the

@@ -16,7 +16,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _native as N
-from ._native import (DprError, F16, F32, FLAG_F16_HALVES, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, FLAG_WIDE_OFFSETS,  # noqa: F401
+from ._native import (DprError, F16, F32, FLAG_F16_HALVES, FLAG_NO_GRAPH, FLAG_NO_SKIP, FLAG_PLAIN, FLAG_QUEUE_COVERAGE,
+                      FLAG_WIDE_OFFSETS,  # noqa: F401
                       check, lib)
 
 __all__ = ["Device", "World", "Frame", "DprError", "composite", "Params", "to_c_camera", "render_train",
@@ -307,6 +308,13 @@ class World:
 
     def set_batch_tile(self, tw, th):
         check(lib.dpr_set_batch_tile(self.h, tw, th))
+
+    def batch_coverage(self):
+        """(items, items taken once, fragment slots, slots written once) of the last
+        batched render, which must have run with FLAG_QUEUE_COVERAGE."""
+        out = (C.c_int64 * 4)()
+        check(lib.dpr_batch_coverage(self.h, out))
+        return tuple(out)
 
     def batch_timings(self):
         """(march_ms, composite_ms) of the last batched render, from HIP events."""

@@ -31,6 +31,7 @@ STATUS = {0: "DPR_OK", -1: "DPR_ERR_INVALID_ARGUMENT", -2: "DPR_ERR_INVALID_STAT
           -4: "DPR_ERR_DEVICE", -5: "DPR_ERR_UNSUPPORTED"}
 F32, F16 = 0, 1
 FLAG_NO_SKIP, FLAG_PLAIN, FLAG_NO_GRAPH, FLAG_WIDE_OFFSETS, FLAG_F16_HALVES = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_QUEUE_COVERAGE = 0x20
 
 
 class DprError(RuntimeError):
@@ -102,6 +103,7 @@ _SIGS = {
     "dpr_autotune_batch": ([P, P, C.c_int32, P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "dpr_set_batch_tile": ([P, C.c_int32, C.c_int32], C.c_int),
     "dpr_batch_timings": ([P, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
+    "dpr_batch_coverage": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "dpr_deep_frame_create": ([P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(P)], C.c_int),
     "dpr_deep_frame_wrap": ([P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.POINTER(P)], C.c_int),
     "dpr_deep_frame_release": ([P], None),

@@ -34,6 +34,8 @@ struct BatchG {
   float4* frag_rgba;
   float* frag_depth;
   int* head;
+  int* item_count;  // coverage counters (DPR_FLAG_QUEUE_COVERAGE), else null
+  int* slot_count;
 };
 
 // Segments between refill checks.  A return to the refill point costs a ballot,
@@ -43,6 +45,9 @@ constexpr int kChunk = 128;
 constexpr int kRefillLanes = 32;
 
 __global__ void reset_head_kernel(int* head) { *head = 0; }
+__global__ void zero_counts_kernel(int* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
 
 template <typename T, bool SKIP, bool WIDE, bool ISO>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void batch_march_kernel(SceneG sc, BatchG bg, const float4* __restrict__ tf) {
@@ -79,6 +84,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
           exhausted = true;
           break;
         }
+        if (bg.item_count && lane == 0) atomicAdd(bg.item_count + it, 1);
         const BatchItem I = bg.items[it];
         if (I.cam != cur_cam || I.brick != cur_brick) {
           if (__ballot(active) != 0) {  // drain the current rays first
@@ -113,6 +119,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
         } else {
           bg.frag_rgba[slot] = make_float4(0.f, 0.f, 0.f, 0.f);
           bg.frag_depth[slot] = INFINITY;
+          if (bg.slot_count) atomicAdd(bg.slot_count + slot, 1);
         }
       }
       pool_next += take;
@@ -141,6 +148,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void b
       if (ray_advance<T, SKIP, WIDE, ISO>(sc, bg.bricks[cur_brick], tfb, tfs, r, kChunk, min_lanes)) {
         bg.frag_rgba[slot] = make_float4(r.cr, r.cg, r.cb, 1.f - r.T);
         bg.frag_depth[slot] = (float)r.t_in;
+        if (bg.slot_count) atomicAdd(bg.slot_count + slot, 1);
         active = false;
       }
     }
@@ -264,6 +272,9 @@ struct BatchState {
   float4* frag_rgba = nullptr;
   float* frag_depth = nullptr;
   int* head = nullptr;
+  int* item_count = nullptr;  // queue-coverage counters, allocated on first use
+  int* slot_count = nullptr;
+  bool counted = false;       // the last render counted
   int n_items = 0, n_tiles = 0, max_k = 0;
   int grid[2] = {0, 0};  // persistent grid of the march kernel without / with iso-surface
   hipStream_t cap = nullptr;
@@ -277,7 +288,7 @@ struct BatchState {
   void free_device() {
     for (void* p : {(void*)d_cams, (void*)d_bricks, (void*)d_items, (void*)d_tile_cam, (void*)d_tile_xy,
                     (void*)d_tile_off, (void*)d_tile_items, (void*)d_out_rgba, (void*)d_out_depth,
-                    (void*)frag_rgba, (void*)frag_depth, (void*)head})
+                    (void*)frag_rgba, (void*)frag_depth, (void*)head, (void*)item_count, (void*)slot_count})
       dev_free(p);
     d_cams = nullptr;
     d_bricks = nullptr;
@@ -288,6 +299,8 @@ struct BatchState {
     frag_rgba = nullptr;
     frag_depth = nullptr;
     head = nullptr;
+    item_count = slot_count = nullptr;
+    counted = false;
     drop_graph();
   }
   // 64-bit offsets for every brick if any brick the launch reads needs them
@@ -390,7 +403,7 @@ static const void* march_fn(bool f16, bool skip, bool wide, bool iso) {
   return skip ? march_fn_s<float, true>(wide, iso) : march_fn_s<float, false>(wide, iso);
 }
 
-static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool timed) {
+static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool timed, bool count = false) {
   SceneG sc = make_scene(w);
   BatchG g{};
   g.cams = b->d_cams;
@@ -402,6 +415,13 @@ static hipError_t enqueue_batch(dpr_world w, BatchState* b, hipStream_t st, bool
   g.frag_rgba = b->frag_rgba;
   g.frag_depth = b->frag_depth;
   g.head = b->head;
+  if (count) {
+    const size_t slots = (size_t)b->n_items * b->tile_w * b->tile_h;
+    g.item_count = b->item_count;
+    g.slot_count = b->slot_count;
+    hipLaunchKernelGGL(zero_counts_kernel, dim3(256), dim3(256), 0, st, b->item_count, (size_t)b->n_items);
+    hipLaunchKernelGGL(zero_counts_kernel, dim3(1024), dim3(256), 0, st, b->slot_count, slots);
+  }
   const bool f16 = w->bricks[b->brick_sel >= 0 ? b->brick_sel : 0].dtype == DPR_F16;
   size_t lds = 2 * sizeof(float4) * (size_t)sc.ntf;
   hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, b->head);
@@ -695,6 +715,20 @@ static dpr_status render_batch_state(dpr_world w, BatchState* b, const dpr_camer
     if (s != DPR_OK) return s;
   }
   w->last_batch = b;
+  b->counted = false;
+  if (flags & DPR_FLAG_QUEUE_COVERAGE) {
+    if (!b->item_count) {
+      const size_t slots = (size_t)b->n_items * b->tile_w * b->tile_h;
+      s = dev_alloc((void**)&b->item_count, std::max<size_t>(1, b->n_items) * sizeof(int), "queue coverage counters");
+      if (s != DPR_OK) return s;
+      s = dev_alloc((void**)&b->slot_count, std::max<size_t>(1, slots) * sizeof(int), "queue coverage counters");
+      if (s != DPR_OK) return s;
+    }
+    DPR_HIP(enqueue_batch(w, b, w->dev->stream, true, true));
+    b->timed = true;
+    b->counted = true;
+    return DPR_OK;
+  }
   if (flags & DPR_FLAG_NO_GRAPH) {
     DPR_HIP(enqueue_batch(w, b, w->dev->stream, true));
     b->timed = true;
@@ -715,24 +749,27 @@ static dpr_status render_batch_tiled(dpr_world w, const dpr_camera* cams, int n,
   return render_batch_state(w, w->batch, cams, n, outs, flags, tw, th, deep, rank, -1);
 }
 
+// render-parameter flags the batched paths take from the world
+constexpr uint32_t kBatchFlags = DPR_FLAG_NO_GRAPH | DPR_FLAG_QUEUE_COVERAGE;
+
 // One brick's partial frame through the persistent kernel: items of that brick
 // only (one cached state per brick), every camera tile written by the tile pass
 // (tiles the brick does not cover come out empty).
 dpr_status render_partial_batched(dpr_world w, int id, dpr_frame out) {
   if ((int)w->partial_batch.size() < (int)w->bricks.size()) w->partial_batch.resize(w->bricks.size(), nullptr);
   if (!w->partial_batch[id]) w->partial_batch[id] = new BatchState;
-  return render_batch_state(w, w->partial_batch[id], &w->cam, 1, &out, w->params.flags & DPR_FLAG_NO_GRAPH,
+  return render_batch_state(w, w->partial_batch[id], &w->cam, 1, &out, w->params.flags & kBatchFlags,
                             w->batch_tile_w, w->batch_tile_h, nullptr, -1, id);
 }
 
 dpr_status render_frame_batched(dpr_world w, dpr_frame out) {
-  return render_batch_tiled(w, &w->cam, 1, &out, w->params.flags & DPR_FLAG_NO_GRAPH, w->batch_tile_w,
+  return render_batch_tiled(w, &w->cam, 1, &out, w->params.flags & kBatchFlags, w->batch_tile_w,
                             w->batch_tile_h);
 }
 
 static dpr_status render_deep(dpr_world w, int rank, dpr_deep_frame out) {
   dpr_frame none = nullptr;
-  dpr_status s = render_batch_tiled(w, &w->cam, 1, &none, w->params.flags & DPR_FLAG_NO_GRAPH, w->batch_tile_w,
+  dpr_status s = render_batch_tiled(w, &w->cam, 1, &none, w->params.flags & kBatchFlags, w->batch_tile_w,
                                     w->batch_tile_h, out, rank);
   if (s != DPR_OK) return s;
   out->rank = rank;
@@ -785,6 +822,25 @@ dpr_status dpr_batch_timings(dpr_world w, float* march_ms, float* composite_ms) 
   DPR_HIP(hipEventElapsedTime(&c, b->ev[1], b->ev[2]));
   if (march_ms) *march_ms = a;
   if (composite_ms) *composite_ms = c;
+  return DPR_OK;
+}
+
+dpr_status dpr_batch_coverage(dpr_world w, int64_t out[4]) {
+  if (!w || !out) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_batch_coverage: NULL argument");
+  BatchState* b = w->last_batch;
+  if (!b || !b->counted)
+    return fail(DPR_ERR_INVALID_STATE, "dpr_batch_coverage: the last batched render did not count its queue");
+  const size_t slots = (size_t)b->n_items * b->tile_w * b->tile_h;
+  std::vector<int> items(b->n_items), marks(slots);
+  DPR_HIP(hipStreamSynchronize(w->dev->stream));
+  if (b->n_items > 0) {
+    DPR_HIP(hipMemcpy(items.data(), b->item_count, items.size() * sizeof(int), hipMemcpyDeviceToHost));
+    DPR_HIP(hipMemcpy(marks.data(), b->slot_count, marks.size() * sizeof(int), hipMemcpyDeviceToHost));
+  }
+  out[0] = (int64_t)items.size();
+  out[1] = std::count(items.begin(), items.end(), 1);
+  out[2] = (int64_t)marks.size();
+  out[3] = std::count(marks.begin(), marks.end(), 1);
   return DPR_OK;
 }
 

@@ -279,3 +279,42 @@ def test_batch_refresh_after_recommit(gpu_lib, dpr):
         assert np.array_equal(got[c][0], want[c][0]) and np.array_equal(got[c][1], want[c][1]), c
     w.release()
     w2.release()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_queue_coverage(gpu_lib, dpr, dtype):
+    """With the queue-coverage counters on, every (camera, brick, tile) item of the
+    persistent queue is taken exactly once and every fragment slot written exactly
+    once -- for a 4-camera batch over 7 uneven bricks (ragged frame, eye inside the
+    volume), for dpr_render_frame and for one brick's dpr_render_partial -- and the
+    frames are the same bits as without the counters."""
+    dims, vol, boxes, tf = _scene(dtype)
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cams = _cams(dims)
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0])
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    w.render_batch(cams, frames)
+    want = [frame_np(f)[:2] for f in frames]
+    w.render_batch(cams, frames, flags=dpr.FLAG_QUEUE_COVERAGE)
+    items, items_once, slots, slots_once = w.batch_coverage()
+    log(f"  batch: {items} items, {slots} fragment slots")
+    assert items > len(boxes) and items_once == items and slots_once == slots == items * 64
+    for f, (a, b) in zip(frames, want):
+        got = frame_np(f)[:2]
+        assert np.array_equal(got[0], a) and np.array_equal(got[1], b)
+    w.render_batch(cams, frames)   # a graph replay counts nothing
+    with pytest.raises(dpr.DprError):
+        w.batch_coverage()
+    w.set_params(dpr.Params(prm.step_voxels, prm.ert, 16, dpr.FLAG_QUEUE_COVERAGE))
+    w.set_camera(cams[2])
+    w.render_frame(frames[2])
+    items, items_once, slots, slots_once = w.batch_coverage()
+    assert items_once == items > 0 and slots_once == slots
+    assert all(np.array_equal(x, y) for x, y in zip(frame_np(frames[2])[:2], want[2]))
+    part = dpr.Frame(gpu_lib, cams[2].width, cams[2].height)
+    w.render_partial(3, part)
+    items, items_once, slots, slots_once = w.batch_coverage()
+    assert items_once == items > 0 and slots_once == slots
+    for f in frames + [part]:
+        f.release()
+    w.release()
