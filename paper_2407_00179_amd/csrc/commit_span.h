@@ -11,8 +11,9 @@ namespace dpr {
 constexpr int kCmCols = 128;  // stored x-voxels of a commit wave's span (16 lanes x 8)
 
 // Window, write core and loaded range of macrocells [m0, m1) along one axis of n
-// stored voxels whose first owned voxel is stored at g (align: 4 for x-runs, 2
-// for row pairs).  Macrocell m covers owned voxels [mc m - 1, mc m + mc], clipped
+// stored voxels whose first owned voxel is stored at g (align: 2 for the row
+// pairs of y and z; the kernel takes y one macrocell at a time and derives its z
+// stages from it).  Macrocell m covers owned voxels [mc m - 1, mc m + mc], clipped
 // to the stored range; the cores of consecutive spans partition [0, n) (the first
 // extended down to 0, the last up to n); the loaded range covers the window and
 // every aligned group whose first voxel lies in the core.
