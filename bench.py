@@ -24,9 +24,9 @@ frames, iso-surfaces and path tracing.
 
 The CPU baseline (the FP64 oracle, not tuned) runs last, over a spawned pool of
 host processes reading the same input bytes from shared memory: the render on a
-pixel sample of the headline brick, the K=128 composite on a band of rows, and
-the gradient on a pixel sample of one 512x512 camera of the 256^3 training
-workload.
+pixel sample of the headline brick, the K=128 composite on a band of rows, the
+K=8 composite of the 512^3 step's partial frames in full, and the gradient on a
+pixel sample of one 512x512 camera of the 256^3 training workload.
 """
 
 from __future__ import annotations
@@ -235,7 +235,7 @@ def copy_ceiling(torch, nbytes=2 << 30, reps=10):
 
 
 # ---------------------------------------------------------------- secondary: 512^3 FP32, 2x2x2 bricks
-def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam):
+def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam, keep_host=False):
     w = dpr.World(dev, dims)
     w.set_params(dpr.Params(cfg.step_voxels, cfg.ert, cfg.macrocell, dpr.FLAG_NO_GRAPH))
     for b in vol_bricks:
@@ -274,11 +274,16 @@ def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam):
     live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
     comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
     ms_comp8 = _timed(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), max(3, args.steps))
+    # the 8 partial frames on the host for the oracle's K = 8 composite leg
+    k8 = None
+    if keep_host:
+        k8 = dict(rgba=torch.stack([f.rgba for f in parts]).cpu().numpy(),
+                  depth=torch.stack([f.depth for f in parts]).cpu().numpy(), ids=np.arange(K))
     w.release()
     for f in parts + [out]:
         f.release()
     march = float(np.mean(march_ms))
-    return dict(workload="512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, step 0.5 "
+    return k8, dict(workload="512^3 FP32 blob+noise volume, 2x2x2 bricks (257^3 stored, 1 ghost), 1024x1024, step 0.5 "
                          "voxel, ERT 0.99; per step: commit, majorants, batched march of the 8 bricks, tile composite",
                 logical_samples=total, ms_per_step=ms_step, msamples_step=total / ms_step / 1e3,
                 ms_batch_march=march, msamples_march=total / march / 1e3,
@@ -587,9 +592,9 @@ def _leg_render(job):
 
 def _leg_composite(job):
     import oracle
-    c0, c1, ids = job
-    rgba = np.asarray(_W["band_rgba"][:, :, c0:c1])
-    depth = np.asarray(_W["band_depth"][:, :, c0:c1])
+    name, c0, c1, ids = job
+    rgba = np.asarray(_W[name + "_rgba"][:, :, c0:c1])
+    depth = np.asarray(_W[name + "_depth"][:, :, c0:c1])
     oracle.composite(rgba, depth, ids)
     return 0
 
@@ -617,7 +622,7 @@ def _segments(cam, dims, step_voxels, px, py):
     return int(np.sum(np.where(hit, np.maximum(n, 0), 0)))
 
 
-def cpu_baseline(args, host_volume, band, cam5, tf5):
+def cpu_baseline(args, host_volume, band, cam5, tf5, k8=None):
     import oracle
     from synth import fibonacci_cameras
     cores = min(16, len(os.sched_getaffinity(0)))
@@ -630,6 +635,10 @@ def cpu_baseline(args, host_volume, band, cam5, tf5):
         np.save(paths["volume"], host_volume)
         np.save(paths["band_rgba"], band["rgba"])
         np.save(paths["band_depth"], band["depth"])
+        if k8 is not None:
+            paths.update(k8_rgba=os.path.join(shm, "k8_rgba.npy"), k8_depth=os.path.join(shm, "k8_depth.npy"))
+            np.save(paths["k8_rgba"], k8["rgba"])
+            np.save(paths["k8_depth"], k8["depth"])
         blobs = make_blobs(cfg4.dims, cfg4.seeds["volume"], cfg4.n_blobs, cfg4.s_range, cfg4.a_range)
         np.save(paths["train_volume"], make_volume_small(cfg4.dims, blobs, cfg4.seeds["volume"], cfg4.noise_amp))
         legs = {}
@@ -653,12 +662,24 @@ def cpu_baseline(args, host_volume, band, cam5, tf5):
             live = int(np.isfinite(band["depth"]).sum())
             cols = np.array_split(np.arange(Wd), 4 * cores)
             t0 = time.perf_counter()
-            pool.map(_leg_composite, [(int(c[0]), int(c[-1]) + 1, band["ids"]) for c in cols], chunksize=1)
+            pool.map(_leg_composite, [("band", int(c[0]), int(c[-1]) + 1, band["ids"]) for c in cols], chunksize=1)
             dt = time.perf_counter() - t0
             alg = K * R * Wd * 4 + live * 16 + R * Wd * 20
             legs["composite_k128"] = dict(value=alg / dt / 1e9, unit="GB/s", seconds=dt, algorithmic_bytes=alg,
                                           sample=f"rows {band['rows'][0]}..{band['rows'][1] - 1} of the 128 "
                                                  f"3840x2160 frames ({R * Wd} pixels)")
+            # composite: the 8 partial frames of the 512^3 step, every pixel
+            if k8 is not None:
+                K8, H8, W8 = k8["depth"].shape
+                live8 = int(np.isfinite(k8["depth"]).sum())
+                cols8 = np.array_split(np.arange(W8), 4 * cores)
+                t0 = time.perf_counter()
+                pool.map(_leg_composite, [("k8", int(c[0]), int(c[-1]) + 1, k8["ids"]) for c in cols8], chunksize=1)
+                dt = time.perf_counter() - t0
+                alg8 = K8 * H8 * W8 * 4 + live8 * 16 + H8 * W8 * 20
+                legs["composite_k8"] = dict(value=alg8 / dt / 1e9, unit="GB/s", seconds=dt, algorithmic_bytes=alg8,
+                                            sample=f"all {H8 * W8} pixels of the 8 partial {W8}x{H8} frames of the "
+                                                   f"512^3 FP32 step")
             # gradient: one 512x512 camera of the 256^3 training volume, every gs-th pixel
             gs = 4
             cam4 = fibonacci_cameras(cfg4.dims, cfg4.n_cams, *cfg4.image)[0]
@@ -794,6 +815,7 @@ def main():
     tf = make_tf(cfg.seeds["tf"])
     cam = orbit_camera(dims, *cfg.image)
     bricks = None
+    k8 = None
     if any(s in secs for s in ("cfg2", "batch", "iso")):
         log("generating the 512^3 volume and its 8 bricks")
         blobs = make_blobs(dims, cfg.seeds["volume"], cfg.n_blobs, cfg.s_range, cfg.a_range)
@@ -802,7 +824,8 @@ def main():
         del vol
     if "cfg2" in secs:
         log("GPU: 512^3 FP32 2x2x2 step")
-        line["step_cfg2"] = bench_cfg2_step(args, dpr, torch, dev, bricks, dims, tf, cfg, cam)
+        k8, line["step_cfg2"] = bench_cfg2_step(args, dpr, torch, dev, bricks, dims, tf, cfg, cam,
+                                                keep_host=not args.no_cpu)
     if "batch" in secs:
         log("GPU: batched renderer vs plain launches on the 512^3 2x2x2 workload")
         w = dpr.World(dev, dims)
@@ -830,8 +853,8 @@ def main():
         line["deep_8ranks"] = bench_deep(args, dpr, torch, dev)
     dev.release()
     if not args.no_cpu:
-        log("CPU oracle baseline (render, K=128 composite and gradient legs)")
-        line["cpu_baseline"] = cpu_baseline(args, host, band, cam5, tf5)
+        log("CPU oracle baseline (render, K=128 and K=8 composite and gradient legs)")
+        line["cpu_baseline"] = cpu_baseline(args, host, band, cam5, tf5, k8)
         log(f"CPU oracle: {line['cpu_baseline']['value']:.2f} Msamples/s on {line['cpu_baseline']['cores']} cores")
     print(json.dumps(line), flush=True)
 

@@ -302,10 +302,24 @@ dpr_status dpr_render_frame(dpr_world, dpr_frame out);
  * The results equal dpr_render_frame per camera bit for bit.                   */
 dpr_status dpr_render_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_frame* outs, uint32_t flags);
 /* Time the candidate tile shapes for this world and camera batch on the GPU and
- * keep the fastest for later dpr_render_batch calls; writes the chosen shape.  */
+ * keep the fastest for later dpr_render_batch calls; writes the chosen shape.
+ * When the environment variable DPR_TUNE_CACHE names a file, the choice is
+ * looked up there first (no timing) and stored there after timing, keyed by the
+ * device (architecture, CU count) and the shape of the work: voxel type and
+ * layout, each brick's stored extent, each camera's image size, step, ERT
+ * threshold and macrocell edge (not the camera poses).                          */
 dpr_status dpr_autotune_batch(dpr_world, const dpr_camera* cams, int32_t n, dpr_frame* outs,
                               int32_t* tile_w, int32_t* tile_h);
 /* Force a tile shape (tile_w * tile_h must be a multiple of 64, <= 1024).      */
+/* The tile-shape cache of dpr_autotune_batch (host only, needs no GPU): a JSON
+ * object {"version": 1, "entries": {"<key>": [tile_w, tile_h], ...}} in the file
+ * `path`.  lookup sets *found to 1 and writes the shape when `key` is there, else
+ * *found = 0 (also for a missing or unreadable file).  store adds or replaces
+ * the entry, keeping the others, and rewrites the file whole (through a
+ * temporary file renamed over it); an unreadable file is replaced.  Keys hold no
+ * quote or backslash (DPR_ERR_INVALID_ARGUMENT).                                 */
+dpr_status dpr_tune_cache_lookup(const char* path, const char* key, int32_t* found, int32_t* tile_w, int32_t* tile_h);
+dpr_status dpr_tune_cache_store(const char* path, const char* key, int32_t tile_w, int32_t tile_h);
 dpr_status dpr_set_batch_tile(dpr_world, int32_t tile_w, int32_t tile_h);
 /* Durations of the march kernel and of the tile compositor of the last batched
  * render (dpr_render_batch with DPR_FLAG_NO_GRAPH, or dpr_render_frame or

@@ -104,6 +104,8 @@ _SIGS = {
     "dpr_set_batch_tile": ([P, C.c_int32, C.c_int32], C.c_int),
     "dpr_batch_timings": ([P, C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
     "dpr_batch_coverage": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
+    "dpr_tune_cache_lookup": ([C.c_char_p, C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "dpr_tune_cache_store": ([C.c_char_p, C.c_char_p, C.c_int32, C.c_int32], C.c_int),
     "dpr_deep_frame_create": ([P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(P)], C.c_int),
     "dpr_deep_frame_wrap": ([P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.POINTER(P)], C.c_int),
     "dpr_deep_frame_release": ([P], None),

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "composite.h"
@@ -857,6 +858,32 @@ dpr_status dpr_autotune_batch(dpr_world w, const dpr_camera* cams, int32_t n, dp
                               int32_t* th_out) {
   dpr_status s = check_batch_args(w, cams, n, outs);
   if (s != DPR_OK) return s;
+  // the persisted choice for this device and shape of work, if any
+  const char* cache = getenv("DPR_TUNE_CACHE");
+  std::string key;
+  if (cache && cache[0]) {
+    const Brick& b0 = w->bricks[0];
+    key = "gfx950 cu" + std::to_string(w->dev->cu_count) +
+          (b0.dtype == DPR_F16 ? (b0.half16 ? " f16-2byte" : " f16-pairs") : " f32") + " bricks";
+    for (const auto& br : w->bricks)
+      key += " " + std::to_string(br.sdim[0]) + "x" + std::to_string(br.sdim[1]) + "x" + std::to_string(br.sdim[2]);
+    key += " cameras";
+    for (int c = 0; c < n; ++c) key += " " + std::to_string(cams[c].width) + "x" + std::to_string(cams[c].height);
+    char prm[128];
+    snprintf(prm, sizeof prm, " step %g ert %g mc %d flags %u", w->params.step_voxels, w->params.ert_threshold,
+             w->params.macrocell_cells, w->params.flags & (DPR_FLAG_NO_SKIP | DPR_FLAG_WIDE_OFFSETS));
+    key += prm;
+    int32_t found = 0, cw = 0, ch = 0;
+    s = dpr_tune_cache_lookup(cache, key.c_str(), &found, &cw, &ch);
+    if (s != DPR_OK) return s;
+    if (found && dpr_set_batch_tile(w, cw, ch) == DPR_OK) {
+      s = render_batch_tiled(w, cams, n, outs, 0, cw, ch);  // leave the chosen shape built
+      if (s != DPR_OK) return s;
+      if (tw_out) *tw_out = cw;
+      if (th_out) *th_out = ch;
+      return DPR_OK;
+    }
+  }
   static const int cand[][2] = {{8, 8}, {16, 8}, {16, 16}, {32, 16}, {32, 32}};
   hipEvent_t e0, e1;
   DPR_HIP(hipEventCreate(&e0));
@@ -889,6 +916,10 @@ dpr_status dpr_autotune_batch(dpr_world w, const dpr_camera* cams, int32_t n, dp
   w->batch_tile_h = bh;
   s = render_batch_tiled(w, cams, n, outs, 0, bw, bh);  // leave the chosen shape built
   if (s != DPR_OK) return s;
+  if (!key.empty()) {
+    s = dpr_tune_cache_store(cache, key.c_str(), bw, bh);
+    if (s != DPR_OK) return s;
+  }
   if (tw_out) *tw_out = bw;
   if (th_out) *th_out = bh;
   return DPR_OK;

@@ -1,12 +1,17 @@
 // C ABI implementation: devices, worlds, bricks, frames, validation and the
 // per-brick render / composite entry points.
+#include <unistd.h>
+
 #include <algorithm>
 #include <atomic>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <numeric>
+#include <string>
 
 #include "runtime.hpp"
 
@@ -334,6 +339,107 @@ extern "C" {
 
 const char* dpr_last_error(void) { return g_last_error.c_str(); }
 const char* dpr_version(void) { return "dpr 0.1 gfx950"; }
+
+// ---------------------------------------------------------------- tile-shape cache
+// {"version": 1, "entries": {"<key>": [w, h], ...}}; keys carry no quote or backslash.
+static bool tune_cache_read(const char* path, std::map<std::string, std::pair<int, int>>& out) {
+  out.clear();
+  FILE* f = fopen(path, "rb");
+  if (!f) return false;
+  std::string txt;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+  fclose(f);
+  size_t i = txt.find("\"entries\"");
+  if (i == std::string::npos) return false;
+  i = txt.find('{', i);
+  if (i == std::string::npos) return false;
+  ++i;
+  auto ws = [&]() {
+    while (i < txt.size() && isspace((unsigned char)txt[i])) ++i;
+  };
+  auto integer = [&](int& v) {
+    ws();
+    size_t j = i;
+    while (j < txt.size() && (isdigit((unsigned char)txt[j]) || (j == i && txt[j] == '-'))) ++j;
+    if (j == i) return false;
+    v = atoi(txt.substr(i, j - i).c_str());
+    i = j;
+    return true;
+  };
+  while (true) {
+    ws();
+    if (i >= txt.size()) return false;
+    if (txt[i] == '}') return true;
+    if (txt[i] == ',') {
+      ++i;
+      continue;
+    }
+    if (txt[i] != '"') return false;
+    const size_t k1 = txt.find('"', i + 1);
+    if (k1 == std::string::npos) return false;
+    const std::string key = txt.substr(i + 1, k1 - i - 1);
+    i = k1 + 1;
+    ws();
+    if (i >= txt.size() || txt[i] != ':') return false;
+    ++i;
+    ws();
+    if (i >= txt.size() || txt[i] != '[') return false;
+    ++i;
+    int w = 0, h = 0;
+    if (!integer(w)) return false;
+    ws();
+    if (i >= txt.size() || txt[i] != ',') return false;
+    ++i;
+    if (!integer(h)) return false;
+    ws();
+    if (i >= txt.size() || txt[i] != ']') return false;
+    ++i;
+    out[key] = {w, h};
+  }
+}
+
+static bool tune_key_ok(const char* key) { return key && !strpbrk(key, "\"\\") && key[0]; }
+
+dpr_status dpr_tune_cache_lookup(const char* path, const char* key, int32_t* found, int32_t* tw, int32_t* th) {
+  if (!path || !found || !tw || !th || !tune_key_ok(key))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_tune_cache_lookup: NULL argument or a key with a quote");
+  std::map<std::string, std::pair<int, int>> m;
+  tune_cache_read(path, m);
+  auto it = m.find(key);
+  *found = it != m.end();
+  if (*found) {
+    *tw = it->second.first;
+    *th = it->second.second;
+  }
+  return DPR_OK;
+}
+
+dpr_status dpr_tune_cache_store(const char* path, const char* key, int32_t tw, int32_t th) {
+  if (!path || !tune_key_ok(key))
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_tune_cache_store: NULL argument or a key with a quote");
+  std::map<std::string, std::pair<int, int>> m;
+  tune_cache_read(path, m);  // an unreadable file is replaced
+  m[key] = {tw, th};
+  std::string txt = "{\"version\": 1, \"entries\": {";
+  bool first = true;
+  for (const auto& e : m) {
+    txt += first ? "\n  \"" : ",\n  \"";
+    first = false;
+    txt += e.first + "\": [" + std::to_string(e.second.first) + ", " + std::to_string(e.second.second) + "]";
+  }
+  txt += "\n}}\n";
+  const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_tune_cache_store: cannot write %s", tmp.c_str());
+  const bool ok = fwrite(txt.data(), 1, txt.size(), f) == txt.size();
+  if (fclose(f) != 0 || !ok || rename(tmp.c_str(), path) != 0) {
+    remove(tmp.c_str());
+    return fail(DPR_ERR_INVALID_ARGUMENT, "dpr_tune_cache_store: cannot write %s", path);
+  }
+  return DPR_OK;
+}
 
 dpr_status dpr_alloc_stats(int64_t* allocations, int64_t* live) {
   if (allocations) *allocations = g_alloc_count.load();

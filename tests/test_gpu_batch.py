@@ -318,3 +318,34 @@ def test_queue_coverage(gpu_lib, dpr, dtype):
     for f in frames + [part]:
         f.release()
     w.release()
+
+
+def test_autotune_cache(gpu_lib, dpr, tmp_path, monkeypatch):
+    """With DPR_TUNE_CACHE set, the autotuner stores its choice under a key of the
+    device and the shape of the work, and a later call for the same shape takes
+    the stored shape without timing (shown by planting another shape)."""
+    import json
+    dims, vol, boxes, tf = _scene()
+    prm = RenderParams(0.5, 0.99, 20.0)
+    cams = _cams(dims)[:2]
+    path = tmp_path / "tiles.json"
+    monkeypatch.setenv("DPR_TUNE_CACHE", str(path))
+    w = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0])
+    frames = [dpr.Frame(gpu_lib, c.width, c.height) for c in cams]
+    tw, th = w.autotune_batch(cams, frames)
+    entries = json.loads(path.read_text())["entries"]
+    assert list(entries.values()) == [[tw, th]]
+    key = next(iter(entries))
+    log(f"  cache key {key!r} -> {tw}x{th}")
+    assert key.startswith("gfx950 cu") and "cameras 96x80 131x67" in key
+    other = (32, 32) if (tw, th) != (32, 32) else (8, 8)
+    dpr.check(dpr.lib.dpr_tune_cache_store(str(path).encode(), key.encode(), *other))
+    w2 = make_world(dpr, gpu_lib, vol, dims, boxes, tf, prm, cams[0])
+    assert w2.autotune_batch(cams, frames) == other
+    ref = [frame_np(f)[:2] for f in frames]
+    w.render_batch(cams, frames)
+    assert all(np.array_equal(a[0], frame_np(f)[0]) for a, f in zip(ref, frames))
+    for f in frames:
+        f.release()
+    w.release()
+    w2.release()
