@@ -13,9 +13,12 @@
 // plane orders two bricks identically for every ray; per-rank depth slabs), so
 // nothing is stored per pixel and no LDS staging limits occupancy.  A pixel whose
 // fragments break the tile order is recomposited in exact (depth, id) order with
-// the same arithmetic, so it gets the same bits: for up to 16 sources in place, by
-// repeated selection of its next fragment; for more, through a fix-up list that a
+// the same arithmetic, so it gets the same bits, through a fix-up list that a
 // second pass works off with the fully general per-wave sort (composite_wave).
+//
+// Few sources (K <= 16): one pixel per lane, whose K keys are sorted in registers
+// by a fixed compare-exchange network and composited with the same arithmetic, so
+// again the same bits; no prior pass, no tile order, no fix-up list.
 #include <algorithm>
 
 #include "composite.h"
@@ -214,39 +217,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         zu[u] = zn[u];
       }
     }
-    if constexpr (KMAX <= 16) {
-      // few sources: a pixel off the tile order is recomposited right here by
-      // repeatedly selecting its next fragment in (depth, id rank) order
-      if (live_px && bad) {
-        tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f, zfirst = INFINITY;
-        lz = -INFINITY;
-        lr = -1;
-        for (;;) {
-          float bz = INFINITY;
-          int br = 0x7fffffff, bk = -1;
-          for (int k = 0; k < K; ++k) {
-            const float z = pdepth[k][p];
-            const int r = prank[k];
-            if (z < INFINITY && (z > lz || (z == lz && r > lr)) && (z < bz || (z == bz && r < br))) {
-              bz = z;
-              br = r;
-              bk = k;
-            }
-          }
-          if (bk < 0) break;
-          const float4 f = prgba[bk][p];
-          if (lr < 0) zfirst = bz;
-          cr = fmaf(tr, f.x, cr);
-          cg = fmaf(tr, f.y, cg);
-          cb = fmaf(tr, f.z, cb);
-          ca = fmaf(tr, f.w, ca);
-          tr *= 1.f - f.w;
-          lz = bz;
-          lr = br;
-        }
-        bad = false;
-      }
-    }
     if (live_px) {
       if (bad) {
         const int slot = atomicAdd(fix_count, 1);
@@ -305,6 +275,94 @@ __global__ __launch_bounds__(64) void composite_fixup_kernel(const CompTable* __
   }
 }
 
+// Few sources: lane = pixel.  Keys (depth, id rank), with a fragment that is not
+// live (depth not below +inf, NaN included) keyed +inf, are sorted by Batcher's
+// odd-even merge network over KS slots (padding slots: +inf); the network's
+// indices are compile-time constants once unrolled, so the keys stay in
+// registers.  The id rank and the source index travel as one word (rank << 8 |
+// source; ranks and sources are below 256).  The live fragments' RGBA are then
+// requested 4 at a time in sorted order and composited front to back.  Each lane
+// walks pixels with a grid stride and requests the next pixel's depths before
+// this pixel's RGBA.
+template <int KS>
+__global__ __launch_bounds__(256) void composite_small_kernel(const CompTable* __restrict__ tab, int K, int P,
+                                                              float4* __restrict__ out_rgba,
+                                                              float* __restrict__ out_depth) {
+  // RGBA pointers are picked per lane after the sort, so they sit in LDS; the
+  // depth pointers are wave-uniform and read from the table into scalar registers
+  __shared__ const float4* prgba[KS];
+  __shared__ uint32_t prk[KS];
+  for (int k = threadIdx.x; k < KS; k += blockDim.x) {
+    prgba[k] = k < K ? tab->rgba[k] : nullptr;
+    prk[k] = ((k < K ? (uint32_t)tab->idrank[k] : 0xffffffu) << 8) | (uint32_t)k;
+  }
+  __syncthreads();
+  const int stride = gridDim.x * blockDim.x;
+  auto load_depths = [&](int pp, float* z) {
+#pragma unroll
+    for (int u = 0; u < KS; ++u) z[u] = (u < K && pp < P) ? ld_global(tab->depth[u], pp) : INFINITY;
+  };
+  float zc[KS];
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  load_depths(p, zc);
+  for (; p < P; p += stride) {
+    float zn[KS];
+    load_depths(p + stride, zn);
+    float z[KS];
+    uint32_t rk[KS];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      z[u] = zc[u] < INFINITY ? zc[u] : INFINITY;
+      rk[u] = prk[u];
+    }
+#pragma unroll
+    for (int q = 1; q < KS; q <<= 1) {
+#pragma unroll
+      for (int d = q; d >= 1; d >>= 1) {
+#pragma unroll
+        for (int j = d % q; j + d < KS; j += 2 * d) {
+#pragma unroll
+          for (int i = 0; i < d && i + j + d < KS; ++i) {
+            const int a = i + j, b = i + j + d;
+            if ((a / (2 * q)) == (b / (2 * q))) {
+              const bool sw = z[b] < z[a] || (z[b] == z[a] && rk[b] < rk[a]);
+              const float za = z[a], zb = z[b];
+              const uint32_t ra = rk[a], rb = rk[b];
+              z[a] = sw ? zb : za;
+              z[b] = sw ? za : zb;
+              rk[a] = sw ? rb : ra;
+              rk[b] = sw ? ra : rb;
+            }
+          }
+        }
+      }
+    }
+    float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f;
+#pragma unroll
+    for (int b0 = 0; b0 < KS; b0 += 4) {
+      if (!(z[b0] < INFINITY)) break;  // sorted: no live fragment from here on
+      float4 f[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        f[u] = z[b0 + u] < INFINITY ? prgba[rk[b0 + u] & 0xffu][p] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (z[b0 + u] < INFINITY) {
+          cr = fmaf(tr, f[u].x, cr);
+          cg = fmaf(tr, f[u].y, cg);
+          cb = fmaf(tr, f[u].z, cb);
+          ca = fmaf(tr, f[u].w, ca);
+          tr *= 1.f - f[u].w;
+        }
+      }
+    }
+    out_rgba[p] = make_float4(cr, cg, cb, ca);
+    out_depth[p] = z[0];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) zc[u] = zn[u];
+  }
+}
+
 // Resident waves per SIMD of the fast kernel: the register budget that keeps
 // every workgroup of the persistent grid resident at once.
 constexpr int kFastWavesPerSimd = 5;
@@ -322,9 +380,8 @@ static void launch_k(const CompTable* tab, int k, int n_pixels, float4* out_rgba
   const int blocks = (n_strips + per - 1) / per;
   hipLaunchKernelGGL((composite_fast_kernel<KMAX, 8, kFastWavesPerSimd>), dim3(blocks), dim3(256), 0, st, tab, k,
                      n_pixels, prior, out_rgba, out_depth, fix_count, fix_list, per);
-  if constexpr (KMAX > 16)
-    hipLaunchKernelGGL(composite_fixup_kernel<KMAX>, dim3(cu_count), dim3(64), 0, st, tab, k, out_rgba, out_depth,
-                       fix_count, fix_list);
+  hipLaunchKernelGGL(composite_fixup_kernel<KMAX>, dim3(cu_count), dim3(64), 0, st, tab, k, out_rgba, out_depth,
+                     fix_count, fix_list);
 }
 
 // Merge of deep frames (dpr_composite_deep).  Table entry r describes part r:
@@ -440,10 +497,28 @@ hipError_t launch_composite_deep(const CompTable* table_dev, int parts, int n_pi
   return hipGetLastError();
 }
 
+template <int KS>
+static void launch_small(const CompTable* tab, int k, int n_pixels, float4* out_rgba, float* out_depth, int cu_count,
+                         hipStream_t st) {
+  if (n_pixels <= 0) return;
+  // one resident grid (the workgroups a CU holds at once, as the runtime reports
+  // for this kernel), each lane walking a few pixels with a grid stride
+  static const int per_cu = [] {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, composite_small_kernel<KS>, 256, 0) != hipSuccess) b = 4;
+    return std::max(1, b);
+  }();
+  const int blocks = (int)std::min<long long>(((long long)n_pixels + 255) / 256, (long long)cu_count * per_cu);
+  hipLaunchKernelGGL(composite_small_kernel<KS>, dim3(blocks), dim3(256), 0, st, tab, k, n_pixels, out_rgba,
+                     out_depth);
+}
+
 hipError_t launch_composite(const CompTable* table_dev, int k, int n_pixels, float4* out_rgba, float* out_depth,
                             int* fix_count, int* fix_list, float* prior, int cu_count, hipStream_t st) {
-  if (k <= 16)
-    launch_k<16>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, prior, cu_count, st);
+  if (k <= 8)
+    launch_small<8>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
+  else if (k <= 16)
+    launch_small<16>(table_dev, k, n_pixels, out_rgba, out_depth, cu_count, st);
   else if (k <= 64)
     launch_k<64>(table_dev, k, n_pixels, out_rgba, out_depth, fix_count, fix_list, prior, cu_count, st);
   else if (k <= 128)

@@ -86,6 +86,41 @@ def test_permutation_invariance_and_ties(gpu_lib, dpr):
         assert np.array_equal(got, ref) and np.array_equal(gz, rz)
 
 
+@pytest.mark.parametrize("K", [1, 2, 8, 9, 16])
+def test_small_k_kernel_equals_tile_order_path(gpu_lib, dpr, K):
+    """Up to 16 sources are composited by sorting each pixel's keys in registers;
+    the same frames padded with empty ones to 17 sources take the tile-order path.
+    Both give the same bits, also with exact depth ties (the id decides) and NaN
+    depths (no fragment), and match the oracle."""
+    import torch
+    W, H = 97, 61
+    log(f"small-K composite K={K}")
+    rgba, depth, frames = _frames(dpr, gpu_lib, K, W, H, seed=300 + K)
+    depth.copy_(torch.where(torch.isfinite(depth), torch.round(depth * 8) / 8, depth))
+    depth[0, ::7, ::5] = float("nan")
+    ids = np.random.default_rng(K).permutation(500)[:K]
+    out = dpr.Frame(gpu_lib, W, H)
+    dpr.composite(gpu_lib, frames, out, ids=ids)
+    got, gz, _ = frame_np(out)
+    n_pad = 17 - K
+    er = torch.zeros((n_pad, H, W, 4), dtype=torch.float32, device=gpu_lib.torch_device)
+    ez = torch.full((n_pad, H, W), float("inf"), dtype=torch.float32, device=gpu_lib.torch_device)
+    pads = [dpr.Frame(gpu_lib, W, H, rgba=er[i], depth=ez[i]) for i in range(n_pad)]
+    out17 = dpr.Frame(gpu_lib, W, H)
+    dpr.composite(gpu_lib, frames + pads, out17, ids=list(ids) + list(range(1000, 1000 + n_pad)))
+    ref, rz, _ = frame_np(out17)
+    assert np.array_equal(got, ref) and np.array_equal(gz, rz)
+    clean = torch.where(torch.isnan(depth), torch.full_like(depth, float("inf")), depth)
+    want, wz = _oracle(rgba, clean, ids)
+    assert np.max(np.abs(got - want)) <= 2e-6
+    assert np.array_equal(gz, wz.astype(np.float32).astype(np.float64))
+    for s in range(2):
+        perm = np.random.default_rng(s).permutation(K)
+        dpr.composite(gpu_lib, [frames[i] for i in perm], out, ids=ids[perm])
+        pg, pz, _ = frame_np(out)
+        assert np.array_equal(pg, got) and np.array_equal(pz, gz)
+
+
 def test_composite_rejects_bad_arguments(gpu_lib, dpr):
     rgba, depth, frames = _frames(dpr, gpu_lib, 3, 16, 16, seed=1)
     out = dpr.Frame(gpu_lib, 16, 16)
