@@ -103,30 +103,24 @@ __device__ __forceinline__ void composite_wave(CompLDS<KMAX>& s, int K, bool liv
                                                RgbaF rgba_of, RankF rank_of, float4& out, float& out_z) {
   const int lane = threadIdx.x & 63;
   const int n = sort_wave<KMAX>(s, K, live_px, depth_of, rank_of);
-  // 4. front-to-back over, RGBA fetched for live fragments only
+  // 4. front-to-back over, RGBA fetched for live fragments only, up to F loads in
+  //    flight per lane (a partial batch is predicated, not walked one load at a time)
   float tr = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, ca = 0.f;
-  constexpr int F = KMAX < 16 ? 8 : 16;  // RGBA loads in flight per lane
-  int i = 0;
-  for (; i + F <= n; i += F) {
+  constexpr int F = KMAX <= 16 ? 8 : 16;
+  for (int i = 0; i < n; i += F) {
     float4 f[F];
 #pragma unroll
-    for (int u = 0; u < F; ++u) f[u] = rgba_of(s.lst[i + u][lane]);
+    for (int u = 0; u < F; ++u) f[u] = i + u < n ? rgba_of(s.lst[i + u][lane]) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int u = 0; u < F; ++u) {
-      cr = fmaf(tr, f[u].x, cr);
-      cg = fmaf(tr, f[u].y, cg);
-      cb = fmaf(tr, f[u].z, cb);
-      ca = fmaf(tr, f[u].w, ca);
-      tr *= 1.f - f[u].w;
+      if (i + u < n) {
+        cr = fmaf(tr, f[u].x, cr);
+        cg = fmaf(tr, f[u].y, cg);
+        cb = fmaf(tr, f[u].z, cb);
+        ca = fmaf(tr, f[u].w, ca);
+        tr *= 1.f - f[u].w;
+      }
     }
-  }
-  for (; i < n; ++i) {
-    const float4 f = rgba_of(s.lst[i][lane]);
-    cr = fmaf(tr, f.x, cr);
-    cg = fmaf(tr, f.y, cg);
-    cb = fmaf(tr, f.z, cb);
-    ca = fmaf(tr, f.w, ca);
-    tr *= 1.f - f.w;
   }
   out = make_float4(cr, cg, cb, ca);
   out_z = n ? s.zs[s.lst[0][lane]][lane] : INFINITY;
