@@ -274,6 +274,7 @@ def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam, keep_
     live = sum(int(torch.isfinite(f.depth).sum().item()) for f in parts)
     comp_bytes = K * W * H * 4 + live * 16 + W * H * 20
     ms_comp8 = _timed(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), max(3, args.steps))
+    ms_comp8_dev = _timed_back_to_back(torch, lambda: dpr.composite(dev, parts, out, ids=list(range(K))), 20)
     # the 8 partial frames on the host for the oracle's K = 8 composite leg
     k8 = None
     if keep_host:
@@ -291,7 +292,12 @@ def bench_cfg2_step(args, dpr, torch, dev, vol_bricks, dims, tf, cfg, cam, keep_
                 ms_plain_8_marches=ms_plain_march, batched_speedup_march=ms_plain_march / march,
                 ms_8_partials_persistent=ms_partials,
                 composite_k8=dict(ms=ms_comp8, algorithmic_bytes=comp_bytes, GBps=comp_bytes / ms_comp8 / 1e6,
-                                  frac_hbm=comp_bytes / ms_comp8 / 1e6 / HBM_PEAK_GBS))
+                                  frac_hbm=comp_bytes / ms_comp8 / 1e6 / HBM_PEAK_GBS,
+                                  how="HIP events around each call (the call's host-side marshalling included)",
+                                  ms_back_to_back=ms_comp8_dev,
+                                  GBps_back_to_back=None if not ms_comp8_dev else comp_bytes / ms_comp8_dev / 1e6,
+                                  frac_hbm_back_to_back=None if not ms_comp8_dev else
+                                  comp_bytes / ms_comp8_dev / 1e6 / HBM_PEAK_GBS))
 
 
 def _timed(torch, fn, n):
@@ -302,6 +308,25 @@ def _timed(torch, fn, n):
         e[1].record()
     torch.cuda.synchronize()
     return float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+
+
+def _timed_back_to_back(torch, fn, n):
+    """Device time per call of ``fn`` with the host's per-call cost hidden: a spin
+    kernel holds the stream while ``n`` calls are enqueued behind it, so the events
+    bracket launches that run back to back.  None where the spin kernel is missing."""
+    sleep = getattr(torch.cuda, "_sleep", None)
+    if sleep is None:
+        return None
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    sleep(50_000_000)
+    e0.record()
+    for _ in range(n):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
 
 
 def _count_samples(dpr, dev, w, cams, n_bricks):
