@@ -121,6 +121,22 @@ def test_small_k_kernel_equals_tile_order_path(gpu_lib, dpr, K):
         assert np.array_equal(pg, got) and np.array_equal(pz, gz)
 
 
+@pytest.mark.parametrize("K", [8, 12])
+def test_small_k_kernel_several_pixels_per_lane(gpu_lib, dpr, K):
+    """A frame larger than one resident grid (each lane walks several pixels and
+    prefetches the next one's depths): every pixel against the oracle."""
+    W, H = 1100, 700
+    log(f"small-K composite K={K} {W}x{H}")
+    rgba, depth, frames = _frames(dpr, gpu_lib, K, W, H, seed=700 + K)
+    ids = np.random.default_rng(K + 1).permutation(300)[:K]
+    out = dpr.Frame(gpu_lib, W, H)
+    dpr.composite(gpu_lib, frames, out, ids=ids)
+    got, gz, _ = frame_np(out)
+    want, wz = _oracle(rgba, depth, ids)
+    assert np.max(np.abs(got - want)) <= 2e-6 * max(1, K / 8)
+    assert np.array_equal(gz, wz.astype(np.float32).astype(np.float64))
+
+
 def test_composite_rejects_bad_arguments(gpu_lib, dpr):
     rgba, depth, frames = _frames(dpr, gpu_lib, 3, 16, 16, seed=1)
     out = dpr.Frame(gpu_lib, 16, 16)
