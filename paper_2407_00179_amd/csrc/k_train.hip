@@ -15,7 +15,8 @@
 // The TF gradient goes to the two lerp entries (weights 1-w, w) through an
 // LDS-private copy flushed once per workgroup; the volume gradient goes to the 8
 // trilinear corners with global atomics, pre-summed in registers while consecutive
-// samples share the same cell.
+// samples share the same cell, and carried over for the corners that the next
+// cell shares with it.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -175,6 +176,38 @@ __device__ __forceinline__ void flush_corners(float* __restrict__ gvol, const Tr
     if (acc[c] != 0.f) atomicAdd(gvol + b + off[c], acc[c]);
 }
 
+// The ray's trilinear cell moved from `cur` by (dx, dy, dz), each in {-1, 0, 1}
+// (a step of at most one voxel).  Corners the old and new cells share keep their
+// sums, moved to their slots in the new cell (slot x + 2 y + 4 z); the others are
+// added to the volume gradient.  A move along one axis thus flushes 4 corners,
+// not 8.
+__device__ __forceinline__ void carry_corners(float* __restrict__ gvol, const TrainG& g, const Stencil& cur,
+                                              float acc[8], int dx, int dy, int dz) {
+  const size_t sx = 1, sy = (size_t)g.dims[0], sz = (size_t)g.dims[0] * g.dims[1];
+  const size_t b = cur.k * sz + cur.j * sy + cur.i;
+  const size_t off[8] = {0, sx, sy, sy + sx, sz, sz + sx, sz + sy, sz + sy + sx};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const bool keep = (unsigned)((c & 1) - dx) <= 1u && (unsigned)(((c >> 1) & 1) - dy) <= 1u &&
+                      (unsigned)((c >> 2) - dz) <= 1u;
+    if (!keep && acc[c] != 0.f) atomicAdd(gvol + b + off[c], acc[c]);
+  }
+  // new slot (x, y, z) <- old slot (x + dx, y + dy, z + dz), zero outside the old cell;
+  // one axis at a time (slot pairs 1, 2 and 4 apart)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int d = a == 0 ? dx : (a == 1 ? dy : dz);
+    const int st = 1 << a;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c & st) continue;
+      const float o0 = acc[c], o1 = acc[c + st];
+      acc[c] = d == 0 ? o0 : (d > 0 ? o1 : 0.f);
+      acc[c + st] = d == 0 ? o1 : (d < 0 ? o0 : 0.f);
+    }
+  }
+}
+
 // TF-gradient replicas in LDS: lanes add into replica (lane & 7); replicas are
 // padded by one float so the same entry of different replicas falls in different
 // banks.  This cuts same-address atomic conflicts (many lanes hit the same few
@@ -226,6 +259,11 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
       Stencil cur;
       cur.i = -1;
       float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      // sample point of the last segment; stepping back by dp gives exactly the
+      // forward's points (fixed-point integers)
+      int64_t p[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) p[a] = r.p[a] + (int64_t)(r.s1 - r.s0) * r.dp[a];
       for (int s = r.s1; s >= r.s0; --s) {
         const int k = s - r.s0;
         // top of a chunk: optical depth after this segment from the forward's record
@@ -233,9 +271,6 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
           tau_after = w[1 + (k + 1) / kCkpt];
           T_next = __expf(-(float)tau_after);
         }
-        int64_t p[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) p[a] = r.p[a] + (int64_t)k * r.dp[a];
         Stencil st;
         const float v = sample_linear(vol, g, p, st);
         const float xr = (v - g.tf_lo) * g.tf_scale;
@@ -283,9 +318,14 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
         const bool inside = xr >= 0.f && xr <= (float)(g.ntf - 1);
         const float gv = inside ? (gA * ts.w + gcR * ts.x + gcG * ts.y + gcB * ts.z) * slope_scale : 0.f;
         if (st.i != cur.i || st.j != cur.j || st.k != cur.k) {
-          if (cur.i >= 0) flush_corners(gvol, g, cur, acc);
+          const int dx = st.i - cur.i, dy = st.j - cur.j, dz = st.k - cur.k;
+          if (cur.i >= 0 && abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) {
+            carry_corners(gvol, g, cur, acc, dx, dy, dz);
+          } else {
+            if (cur.i >= 0) flush_corners(gvol, g, cur, acc);
 #pragma unroll
-          for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+            for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+          }
           cur = st;
         }
         const float ux = st.fx, uy = st.fy, uz = st.fz;
@@ -298,6 +338,8 @@ __global__ __launch_bounds__(256) void train_backward_kernel(TrainG g, const Cam
         acc[5] = fmaf(gv, uz * ly * ux, acc[5]);
         acc[6] = fmaf(gv, uz * uy * lx, acc[6]);
         acc[7] = fmaf(gv, uz * uy * ux, acc[7]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[a] -= r.dp[a];
       }
       if (cur.i >= 0) flush_corners(gvol, g, cur, acc);
     }
