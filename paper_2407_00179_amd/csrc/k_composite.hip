@@ -505,7 +505,10 @@ static void launch_small(const CompTable* tab, int k, int n_pixels, float4* out_
   // for this kernel), each lane walking a few pixels with a grid stride
   static const int per_cu = [] {
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, composite_small_kernel<KS>, 256, 0) != hipSuccess) b = 4;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, composite_small_kernel<KS>, 256, 0) != hipSuccess) {
+      (void)hipGetLastError();  // a guess of 4 is fine; keep the failed query out of the launch's status
+      b = 4;
+    }
     return std::max(1, b);
   }();
   const int blocks = (int)std::min<long long>(((long long)n_pixels + 255) / 256, (long long)cu_count * per_cu);
