@@ -440,13 +440,17 @@ __global__ __launch_bounds__(256) void deep_merge_kernel(const CompTable* __rest
       // exist), and a fragment whose depth is not below +inf (NaN included) is not
       // live, as in the flat compositor
       for (int u = 0; u < 8; ++u) c[u] = r0 + u < R ? min(max(pcount[r0 + u][p], 0), pcap[r0 + u]) : 0;
+      // every part's first layer is requested at once; deeper layers (rare) in the loop
+      float d0[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d0[u] = c[u] > 0 ? pdepth[r0 + u][p] : INFINITY;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (c[u] <= 0) continue;
         const float* dz = pdepth[r0 + u] + p;
         const int kb = pkey[r0 + u];
         for (int l = 0; l < c[u]; ++l) {
-          const float d = dz[(size_t)l * sP];
+          const float d = l == 0 ? d0[u] : dz[(size_t)l * sP];
           if (!(d < INFINITY)) continue;
           ++n;
           const int key = kb | l;
