@@ -7,7 +7,8 @@
  *                           device creation, which must fail cleanly without a
  *                           GPU); prints OK on success.
  *   abi_client render DIR   render the scene described in DIR/scene.txt with
- *                           bricks DIR/brick<i>.f32 and table DIR/tf.f32:
+ *                           bricks DIR/brick<i>.f32 (FP32) or DIR/brick<i>.f16
+ *                           (FP16, raw halves) and table DIR/tf.f32:
  *                           every brick's partial frame (dpr_render_partial),
  *                           their sort-last composite (dpr_composite) and the
  *                           whole frame (dpr_render_frame), written to
@@ -19,6 +20,7 @@
  *   camera EX EY EZ CX CY CZ UX UY UZ FOVY W H
  *   params STEP ERT MACROCELL FLAGS
  *   tf N LO HI DENSITY
+ *   dtype f32|f16
  *   bricks N
  *   then per brick: LO[3] HI[3] GHOST_LO[3] GHOST_HI[3]
  */
@@ -82,15 +84,15 @@ static int run_check(void) {
   return bad ? 1 : 0;
 }
 
-static float* read_floats(const char* path, size_t n) {
+static void* read_elems(const char* path, size_t n, size_t elem) {
   FILE* f = fopen(path, "rb");
-  float* p = NULL;
+  void* p = NULL;
   if (!f) {
     fprintf(stderr, "cannot open %s\n", path);
     return NULL;
   }
-  p = (float*)malloc(n * sizeof(float));
-  if (p && fread(p, sizeof(float), n, f) != n) {
+  p = malloc(n * elem);
+  if (p && fread(p, elem, n, f) != n) {
     fprintf(stderr, "%s: short read\n", path);
     free(p);
     p = NULL;
@@ -121,6 +123,7 @@ struct scene {
   dpr_render_params prm;
   int tf_n;
   float tf_lo, tf_hi, density;
+  int f16;
   int n;
   int64_t lo[MAX_BRICKS][3], hi[MAX_BRICKS][3];
   int32_t glo[MAX_BRICKS][3], ghi[MAX_BRICKS][3];
@@ -145,6 +148,11 @@ static int read_scene(const char* dir, struct scene* s) {
   ok = ok && fscanf(f, " params %f %f %d %u", &s->prm.step_voxels, &s->prm.ert_threshold, &s->prm.macrocell_cells,
                     &s->prm.flags) == 4;
   ok = ok && fscanf(f, " tf %d %f %f %f", &s->tf_n, &s->tf_lo, &s->tf_hi, &s->density) == 4;
+  {
+    char dt[8] = {0};
+    ok = ok && fscanf(f, " dtype %7s", dt) == 1 && (strcmp(dt, "f32") == 0 || strcmp(dt, "f16") == 0);
+    s->f16 = strcmp(dt, "f16") == 0;
+  }
   ok = ok && fscanf(f, " bricks %d", &s->n) == 1 && s->n >= 1 && s->n <= MAX_BRICKS;
   for (i = 0; ok && i < s->n; ++i) {
     long long v[6];
@@ -176,7 +184,7 @@ static int run_render(const char* dir) {
   int i, a;
   if (read_scene(dir, &s)) return 1;
   snprintf(path, sizeof path, "%s/tf.f32", dir);
-  tf = read_floats(path, (size_t)s.tf_n * 4);
+  tf = (float*)read_elems(path, (size_t)s.tf_n * 4, sizeof(float));
   if (!tf) return 1;
   CHECK(dpr_alloc_stats(&allocs0, &live0));
   CHECK(dpr_device_create(0, NULL, &dev));
@@ -185,13 +193,13 @@ static int run_render(const char* dir) {
   for (i = 0; i < s.n; ++i) {
     size_t nv = 1;
     int32_t id = -1;
-    float* vox;
+    void* vox;
     for (a = 0; a < 3; ++a) nv *= (size_t)(s.hi[i][a] - s.lo[i][a] + s.glo[i][a] + s.ghi[i][a]);
-    snprintf(path, sizeof path, "%s/brick%d.f32", dir, i);
-    vox = read_floats(path, nv);
+    snprintf(path, sizeof path, "%s/brick%d.%s", dir, i, s.f16 ? "f16" : "f32");
+    vox = read_elems(path, nv, s.f16 ? 2 : 4);
     if (!vox) return 1;
     /* host memory: the library copies the stored region and the buffer is freed at once */
-    CHECK(dpr_world_add_brick(w, vox, DPR_F32, 0, s.lo[i], s.hi[i], s.glo[i], s.ghi[i], &id));
+    CHECK(dpr_world_add_brick(w, vox, s.f16 ? DPR_F16 : DPR_F32, 0, s.lo[i], s.hi[i], s.glo[i], s.ghi[i], &id));
     free(vox);
     if (id != i) {
       fprintf(stderr, "brick %d got id %d\n", i, (int)id);

@@ -51,13 +51,19 @@ def _read_frame(path, w, h):
 
 
 @pytest.mark.gpu
-def test_c_client_renders_like_the_oracle(tmp_path, gpu_lib):
+@pytest.mark.parametrize("dtype,flags", [("f32", 0), ("f16", 0), ("f16", 0x10)])
+def test_c_client_renders_like_the_oracle(tmp_path, gpu_lib, dtype, flags):
+    """FP32 bricks, FP16 bricks as voxel pairs, and FP16 bricks in the 2-byte
+    layout (DPR_FLAG_F16_HALVES), all from host buffers of a C program."""
     import oracle
     from synth import even_split, extract_brick, make_blobs, make_tf, make_volume_small, orbit_camera
-    from tests.gpu_util import TOL_F32, log, oracle_brick
+    from tests.gpu_util import TOL_F16, TOL_F32, log, oracle_brick
 
     dims = (40, 36, 30)
     vol = make_volume_small(dims, make_blobs(dims, 41, 6, (0.08, 0.25)), 42, 0.02)
+    np_dtype = np.float16 if dtype == "f16" else np.float32
+    vol = vol.astype(np_dtype)
+    tol = TOL_F16 if dtype == "f16" else TOL_F32
     tf = make_tf(2001)
     cam = orbit_camera(dims, 48, 40)
     boxes = even_split(dims, (2, 1, 2))
@@ -65,18 +71,19 @@ def test_c_client_renders_like_the_oracle(tmp_path, gpu_lib):
     lines = [f"dims {dims[0]} {dims[1]} {dims[2]}",
              "camera " + " ".join(repr(float(v)) for v in (*cam.eye, *cam.center, *cam.up, cam.fovy_deg))
              + f" {cam.width} {cam.height}",
-             f"params {prm.step_voxels} {prm.ert} 8 0",
+             f"params {prm.step_voxels} {prm.ert} 8 {flags}",
              f"tf {len(tf)} {prm.tf_lo} {prm.tf_hi} {prm.density}",
+             f"dtype {dtype}",
              f"bricks {len(boxes)}"]
     for i, (lo, hi) in enumerate(boxes):
         b = extract_brick(vol, dims, lo, hi)
-        np.ascontiguousarray(b.data, dtype=np.float32).tofile(str(tmp_path / f"brick{i}.f32"))
+        np.ascontiguousarray(b.data, dtype=np_dtype).tofile(str(tmp_path / f"brick{i}.{dtype}"))
         lines.append(" ".join(str(int(v)) for v in (*lo, *hi, *b.ghost_lo, *b.ghost_hi)))
     np.ascontiguousarray(tf, dtype=np.float32).tofile(str(tmp_path / "tf.f32"))
     (tmp_path / "scene.txt").write_text("\n".join(lines) + "\n")
 
     exe = _build(tmp_path)
-    log(f"C client: {len(boxes)} bricks of {dims} at {cam.width}x{cam.height}")
+    log(f"C client: {len(boxes)} {dtype} bricks of {dims} (flags {flags:#x}) at {cam.width}x{cam.height}")
     r = subprocess.run([exe, "render", str(tmp_path)], capture_output=True, text=True, timeout=300, env=_env())
     assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout + r.stderr
 
@@ -88,7 +95,7 @@ def test_c_client_renders_like_the_oracle(tmp_path, gpu_lib):
         got, gz = _read_frame(str(tmp_path / f"partial{i}.f32"), W, H)
         want, wz, _ = oracle_brick(vol, dims, lo, hi, tf, prm, cam, px, py)
         err = np.max(np.abs(got - want))
-        assert err <= TOL_F32, f"brick {i}: {err:.3e}"
+        assert err <= tol, f"brick {i}: {err:.3e}"
         fin = np.isfinite(wz)
         assert np.array_equal(np.isfinite(gz), fin)
         assert np.max(np.abs(gz[fin] - wz[fin]) / wz[fin], initial=0.0) <= 3e-7
@@ -99,7 +106,7 @@ def test_c_client_renders_like_the_oracle(tmp_path, gpu_lib):
     whole, fz = _read_frame(str(tmp_path / "frame.f32"), W, H)
     err = np.max(np.abs(comp - want_c))
     log(f"  composite max|c-oracle| = {err:.3e}")
-    assert err <= TOL_F32
+    assert err <= tol
     assert np.array_equal(np.isfinite(cz), np.isfinite(want_z))
     # the batched whole-frame render gives the same bits as partials + composite
     assert np.array_equal(whole, comp) and np.array_equal(fz, cz)
